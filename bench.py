@@ -1,0 +1,230 @@
+"""Benchmark of the fused B-TriRT D2Q9 sweep on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one time step of the whole hot path over the grid (pull-stream with bounce-back,
+moments, block relaxation, equilibrium/source/correction, reconstruction, phi), plus the
+Eq. (64) residual reduction every 1000 steps. The workload is the 4096 x 4096 nonlinear
+anisotropic problem in FP64 (the configuration whose working set exceeds the 256 MB
+Infinity Cache, so the HBM roofline applies). Inputs are resident in HBM before timing.
+
+Prints one JSON line. ``value`` is MLUPS (node updates per microsecond); ``roofline`` compares
+the sweep kernel's algorithmic bytes per launch / its average duration with 8 TB/s;
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CHECK_INTERVAL = 1000
+METRIC = "MLUPS and % HBM roofline, batched/served vs plain; p50/p99 solve latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_09813_amd", "csrc", "btrt_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def timed_run(w, precision, steps, warmup):
+    """Warm up, then time exactly ``steps`` steps with HIP events on the library's stream."""
+    import torch
+    from paper_1902_09813_amd import btrt
+
+    prob = btrt.problem_from_workload(w, precision=precision, check_interval=CHECK_INTERVAL)
+    solver = btrt.Solver(prob, w.phi0(), torch_memory=True)  # torch memory + torch's current stream
+    stream = torch.cuda.current_stream()
+    info = solver.info()
+    solver.step(warmup)
+    solver.sync()
+    torch.cuda.synchronize()
+
+    # Events bracket every chunk of sweeps between residual checks, so the sweep's average
+    # duration excludes the reductions.
+    chunks = []
+    done = 0
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    residual = None
+    while done < steps:
+        k = min(CHECK_INTERVAL, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        solver.step(k)
+        b.record(stream)
+        chunks.append((a, b, k))
+        done += k
+        if done % CHECK_INTERVAL == 0:
+            residual = solver.residual()  # Eq. (64), part of the step's work
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in chunks)
+    solver.close()
+    nodes = w.nx * w.ny
+    return {
+        "ms_total": total_ms,
+        "wall_s": wall,
+        "ms_per_step": total_ms / steps,
+        "sweep_ms_avg": sweep_ms / steps,
+        "mlups": nodes * steps / (total_ms * 1e-3) / 1e6,
+        "bytes_per_update": info.bytes_per_update,
+        "nodes": nodes,
+        "residual": residual,
+    }
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
+    from oracle import oracle as O
+    from tests._cases import oracle_problem, oracle_source
+
+    o = O.Oracle(oracle_problem(w), w.phi0(), source=oracle_source(w))
+    t = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t
+    n = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    o.step(n)
+    el = time.perf_counter() - t
+    return {
+        "value": round(w.nx * w.ny * n / el / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": O.threads(),
+        "kind": "oracle",
+        "sample": f"{w.name}: {n} steps of the {w.nx}x{w.ny} grid after 1 warm-up step ({el:.1f} s)",
+    }
+
+
+def traffic_for(precision_name, nodes):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None if the
+    kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    ent = rec.get(precision_name)
+    if not ent or ent.get("nodes") != nodes:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def copy_probe(nbytes):
+    """Device-to-device copy of a known size (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the sweep is measured on a single MI355X; "
+              "multi-GPU runs are not part of this benchmark.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+
+    from paper_1902_09813_amd import btrt
+    from paper_1902_09813_amd import workloads as W
+
+    prec = btrt.F64 if args.precision == "f64" else btrt.F32
+    w = W.c3()
+    print(f"[bench] {w.name} {args.precision}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
+          flush=True)
+    r = timed_run(w, prec, args.steps, args.warmup)
+    bytes_per_launch = r["bytes_per_update"] * r["nodes"]
+    achieved = bytes_per_launch / (r["sweep_ms_avg"] * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "sweep_kernel",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic_for(args.precision, r["nodes"]),
+        "bytes_per_launch": bytes_per_launch,
+        "sweep_ms_avg": round(r["sweep_ms_avg"], 5),
+    }
+    extra = {}
+    if not args.no_extra:
+        other = btrt.F32 if prec == btrt.F64 else btrt.F64
+        name = "f32" if other == btrt.F32 else "f64"
+        print(f"[bench] side measurement: {w.name} {name}", file=sys.stderr, flush=True)
+        r2 = timed_run(w, other, min(args.steps, 2000), 50)
+        extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
+        extra[f"c3_{name}_hbm_frac"] = round(r2["bytes_per_update"] * r2["nodes"] / (r2["sweep_ms_avg"] * 1e-3)
+                                             / 1e9 / HBM_PEAK_GBS, 4)
+        w2 = W.c2()
+        print(f"[bench] side measurement: {w2.name} f64", file=sys.stderr, flush=True)
+        r3 = timed_run(w2, btrt.F64, 2000, 50)
+        extra["c2_f64_mlups"] = round(r3["mlups"], 1)
+        extra["c2_f64_sweep_us"] = round(r3["sweep_ms_avg"] * 1e3, 2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    line = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (seeded 16-Gaussian initial field, lattice units)",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "boundary": "periodic",
+                   "flux": "B = 0.025 phi^2 (1, 1)", "diffusion": "A = diag(0.01, 0.005)(1 + phi^2)",
+                   "k0": 1.0, "k2": 1.0, "residual_check_interval": CHECK_INTERVAL, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+        "residual_at_end": r["residual"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * btrt.h - C ABI of the MI355X (gfx950) library for the block triple-relaxation-time
+ * (B-TriRT) lattice Boltzmann method on the D2Q9 lattice, for nonlinear anisotropic
+ * convection-diffusion equations (Zhao, Wu, Chai & Shi, arXiv:1902.09813).
+ *
+ * The library solves Eq. (1),
+ *     d_t phi + div B(phi) = div[ A(phi) grad . D(phi) ] + S(x),
+ * in lattice units (dx = dt = 1, c = 1, c_s^2 = 1/3), with the evolution equation
+ * Eq. (6) (equivalently its moment form, Eq. (94) with the block relaxation matrix of
+ * Eq. (99)), the equilibrium of Eq. (7), the source of Eq. (8), the correction G of
+ * Eq. (11), streaming as in Eq. (38) and half-way bounce-back for Dirichlet sides
+ * (Eqs. (54)-(56)). K1 follows from A through Eq. (30); k2 may follow the bounce-back
+ * rule of Eq. (62).
+ *
+ * Discretisation choices where the paper leaves the detail open:
+ *   - d_t B in G is the backward difference B(phi(t)) - B(phi(t-1)); at the first step
+ *     phi(t-1) is phi0, so G starts at zero.
+ *   - Sources are time independent, so the Scheme 2 derivative term (Remark III) is 0.
+ *   - A diagonal link leaving through a corner point bounces back with the mean of the
+ *     two walls' values.
+ *   - Node x = (i, j) sits at the cell centre (i + 1/2, j + 1/2); walls lie at 0 and nx
+ *     (resp. ny), as in y_n = (n - 1/2)/N below Eq. (49).
+ *
+ * Conventions for every call:
+ *   - Return value: BTRT_OK (0) or one of the BTRT_E_* codes below; btrt_last_error()
+ *     then holds a one-line message for the calling thread.
+ *   - Host arrays are row major, x fastest: a[j*nx + i] for node (i, j).
+ *   - All host pointers passed in are only read during the call (copied where kept);
+ *     output buffers are owned by the caller.
+ *   - A handle is not thread safe; distinct handles are independent. Work is enqueued on
+ *     the handle's HIP stream; calls documented as synchronising wait for that stream.
+ */
+#ifndef BTRT_H
+#define BTRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------------------ */
+#define BTRT_OK 0
+#define BTRT_E_INVAL 1    /* invalid argument; nothing was allocated or launched */
+#define BTRT_E_NOMEM 2    /* device allocation failed or workspace too small */
+#define BTRT_E_DEVICE 3   /* no usable HIP device, or a HIP call failed */
+#define BTRT_E_UNSTABLE 4 /* a reduction saw NaN/Inf in phi; the handle stays usable */
+#define BTRT_E_STATE 5    /* NULL handle */
+
+/* ---- enumerations ------------------------------------------------------------------ */
+#define BTRT_F64 0 /* populations stored and collided in FP64 */
+#define BTRT_F32 1 /* populations stored and collided in FP32 (reductions stay FP64) */
+
+#define BTRT_PERIODIC 0
+#define BTRT_DIRICHLET 1 /* half-way bounce-back, Eqs. (54)-(56) */
+
+#define BTRT_SRC_NONE 0
+#define BTRT_SRC_FIELD 1 /* S(x) given per node */
+#define BTRT_SRC_SIN 2   /* S = amp sin(kx pi x / nx) sin(ky pi y / ny) at cell centres */
+
+#define BTRT_D_PHI_I 0   /* D(phi) = phi I, the only D the library accepts */
+
+#define BTRT_K2_VALUE 0  /* K2 given explicitly (relax.k2) */
+#define BTRT_K2_HBB 1    /* k2 = 8(k1-2)/(3(k1-4)), Eq. (62); needs A = alpha I constant */
+
+/* ---- problem description ----------------------------------------------------------- */
+typedef struct btrt btrt_t; /* opaque; created by btrt_create, released by btrt_destroy */
+
+typedef struct {
+    int32_t nx, ny;         /* nodes along x and y, each >= 1; nx*ny <= 2^31 - 1 */
+    int32_t precision;      /* BTRT_F64 or BTRT_F32 */
+    int32_t device;         /* HIP device ordinal */
+    void* stream;           /* hipStream_t to enqueue on; NULL: the library creates one */
+    void* workspace;        /* device memory owned by the caller, >= btrt_workspace_size();
+                               NULL: the library allocates and frees its own */
+    size_t workspace_bytes; /* size of workspace in bytes (ignored when workspace is NULL) */
+} btrt_grid_t;
+
+/* B(phi) = a*phi + b*phi^2/2, per component (Eq. (1)). Linear convection with velocity u
+ * is a = u, b = 0; the Burgers flux (phi^2/2)*c is a = 0, b = c. */
+typedef struct {
+    double a[2];
+    double b[2];
+} btrt_flux_t;
+
+/* A(phi) = [[k11, k12], [k12, k22]] * (1 + beta*phi^2) (Eq. (1)); symmetric positive
+ * definite, beta >= 0. Constant when beta == 0. */
+typedef struct {
+    double k11, k12, k22;
+    double beta;
+} btrt_diff_t;
+
+typedef struct {
+    int32_t kind; /* BTRT_D_PHI_I */
+} btrt_dterm_t;
+
+/* Source S of Eq. (8), time independent. FIELD: field[j*nx + i], copied at create. */
+typedef struct {
+    int32_t kind; /* BTRT_SRC_NONE, BTRT_SRC_FIELD or BTRT_SRC_SIN */
+    double amp;
+    int32_t kx, ky;
+    const double* field;
+} btrt_source_t;
+
+/* Sides in the order x-, x+, y-, y+. A periodic side must be paired with its opposite. */
+typedef struct {
+    int32_t type[4];  /* BTRT_PERIODIC or BTRT_DIRICHLET */
+    double value[4];  /* phi_w of a Dirichlet side */
+} btrt_bc_t;
+
+/* Relaxation blocks of Eq. (99): k0 on the S0 block; K2 (row major [[k2_11, k2_12],
+ * [k2_21, k2_22]]) on the second-order block (pxy relaxes with (k2_12 + k2_21)/2);
+ * K1 always from A through Eq. (30). */
+typedef struct {
+    double k0;              /* in (0, 2) */
+    int32_t k2_rule;        /* BTRT_K2_VALUE or BTRT_K2_HBB */
+    double k2[4];           /* used with BTRT_K2_VALUE; k2_11, k2_22, (k2_12+k2_21)/2 in (0, 2) */
+    int32_t check_interval; /* steps between Eq. (64) checks in btrt_solve (>= 1) */
+} btrt_relax_t;
+
+/* Derived constants and sizes of a problem (host-side, no device work). */
+typedef struct {
+    int32_t nx, ny, precision, pitch; /* pitch: padded row length of device planes, elements */
+    int32_t k1_per_node;              /* 1 when K1 depends on phi (beta != 0) */
+    double K1[4];                     /* Eq. (30) at A(phi = 0), row major */
+    double K2[4];                     /* resolved K2 */
+    double k0;
+    size_t workspace_bytes;           /* device bytes a handle needs */
+    double bytes_per_update;          /* algorithmic HBM bytes of one node update */
+    int64_t step;                     /* steps taken (btrt_get_info only) */
+} btrt_info_t;
+
+/* ---- calls --------------------------------------------------------------------------- */
+
+/* Checks a problem and fills *info (optional) without touching any device.
+ * Errors: BTRT_E_INVAL for sizes out of range, unpaired periodic sides, A not SPD or
+ * beta < 0, rates outside (0, 2), BTRT_K2_HBB with a non-isotropic or phi-dependent A,
+ * an unsupported D or source kind, or non-finite values. */
+int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
+                  const btrt_dterm_t* D, const btrt_source_t* R, const btrt_bc_t* bc,
+                  const btrt_relax_t* relax, btrt_info_t* info);
+
+/* Device bytes btrt_create needs for this grid and source (R may be NULL for no source);
+ * 0 when the grid is invalid. */
+size_t btrt_workspace_size(const btrt_grid_t* grid, const btrt_source_t* R);
+
+/* Creates a solver at t = 0 with f = f^eq(phi0) (Section 4: populations start at
+ * equilibrium). phi0: nx*ny host values, copied. On success *out owns the device state.
+ * Errors: those of btrt_validate; non-finite phi0 -> BTRT_E_INVAL; BTRT_E_DEVICE;
+ * BTRT_E_NOMEM. Synchronises. */
+int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
+                const btrt_dterm_t* D, const btrt_source_t* R, const btrt_bc_t* bc,
+                const btrt_relax_t* relax, const double* phi0, btrt_t** out);
+
+/* Enqueues n >= 0 time steps (collide, stream, bounce back) on the handle's stream and
+ * returns without waiting. */
+int btrt_step(btrt_t* h, int64_t n);
+
+/* phi(t) = sum_i f_i(x, t) (Eq. (9)) into phi_out[nx*ny]. Synchronises. */
+int btrt_field(btrt_t* h, double* phi_out);
+
+/* Post-streaming populations f_i(x, t) into f_out[9*nx*ny] as f_out[i*nx*ny + j*nx + x],
+ * i in the velocity order of Eq. (85). Synchronises. */
+int btrt_populations(btrt_t* h, double* f_out);
+
+/* Eq. (64): sum|phi(t) - phi_snap| / sum|phi(t)| in FP64, where phi_snap is phi at the
+ * previous btrt_residual call (phi0 for the first); then phi_snap := phi(t).
+ * Synchronises. BTRT_E_UNSTABLE (with *out = NaN) if phi holds NaN/Inf. */
+int btrt_residual(btrt_t* h, double* out);
+
+/* Against a reference field ref[nx*ny]: out[0] = GRE of Eq. (63), out[1] = max |phi - ref|,
+ * out[2] = sqrt(sum (phi - ref)^2 / sum ref^2). FP64. Synchronises. */
+int btrt_error(btrt_t* h, const double* ref, double out[3]);
+
+/* Runs check_interval steps at a time until the Eq. (64) residual is <= tol or max_steps
+ * steps have been taken. Reports the steps taken and the last residual. Synchronises. */
+int btrt_solve(btrt_t* h, double tol, int64_t max_steps, int64_t* steps_taken, double* residual);
+
+/* Waits for all work enqueued on the handle's stream. */
+int btrt_sync(btrt_t* h);
+
+/* Derived constants plus the number of steps taken. */
+int btrt_get_info(const btrt_t* h, btrt_info_t* info);
+
+/* Frees the handle and the device memory the library allocated. Synchronises. */
+int btrt_destroy(btrt_t* h);
+
+/* Static text for an error code. */
+const char* btrt_strerror(int code);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* btrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTRT_H */

@@ -1,0 +1,265 @@
+"""ctypes binding of libbtrt (include/btrt.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels. PyTorch, when used, only
+provides device memory (a workspace tensor) and the HIP stream the library enqueues on.
+The binding fails loudly when the library is not built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libbtrt.so")
+
+# Constants of include/btrt.h.
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, 1, 2, 3, 4, 5
+F64, F32 = 0, 1
+PERIODIC, DIRICHLET = 0, 1
+SRC_NONE, SRC_FIELD, SRC_SIN = 0, 1, 2
+D_PHI_I = 0
+K2_VALUE, K2_HBB = 0, 1
+
+# Every function include/btrt.h declares.
+EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_field",
+           "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
+           "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Flux(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double * 2), ("b", ctypes.c_double * 2)]
+
+
+class Diff(ctypes.Structure):
+    _fields_ = [("k11", ctypes.c_double), ("k12", ctypes.c_double), ("k22", ctypes.c_double),
+                ("beta", ctypes.c_double)]
+
+
+class DTerm(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("amp", ctypes.c_double), ("kx", ctypes.c_int32),
+                ("ky", ctypes.c_int32), ("field", ctypes.POINTER(ctypes.c_double))]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32 * 4), ("value", ctypes.c_double * 4)]
+
+
+class Relax(ctypes.Structure):
+    _fields_ = [("k0", ctypes.c_double), ("k2_rule", ctypes.c_int32), ("k2", ctypes.c_double * 4),
+                ("check_interval", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("k1_per_node", ctypes.c_int32), ("K1", ctypes.c_double * 4),
+                ("K2", ctypes.c_double * 4), ("k0", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+                ("bytes_per_update", ctypes.c_double), ("step", ctypes.c_int64)]
+
+
+class BtrtError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        self.code = code
+        super().__init__(f"{where}: {msg} (code {code})")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbtrt.so (built by paper_1902_09813_amd/build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1902_09813_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        dp = P(ctypes.c_double)
+        hp = ctypes.c_void_p
+        sig = {
+            "btrt_validate": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), P(Info)], ctypes.c_int),
+            "btrt_workspace_size": ([P(Grid), P(Source)], ctypes.c_size_t),
+            "btrt_create": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, P(hp)], ctypes.c_int),
+            "btrt_step": ([hp, ctypes.c_int64], ctypes.c_int),
+            "btrt_field": ([hp, dp], ctypes.c_int),
+            "btrt_populations": ([hp, dp], ctypes.c_int),
+            "btrt_residual": ([hp, dp], ctypes.c_int),
+            "btrt_error": ([hp, dp, dp], ctypes.c_int),
+            "btrt_solve": ([hp, ctypes.c_double, ctypes.c_int64, P(ctypes.c_int64), dp], ctypes.c_int),
+            "btrt_sync": ([hp], ctypes.c_int),
+            "btrt_get_info": ([hp, P(Info)], ctypes.c_int),
+            "btrt_destroy": ([hp], ctypes.c_int),
+            "btrt_strerror": ([ctypes.c_int], ctypes.c_char_p),
+            "btrt_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        msg = lib().btrt_last_error().decode() or lib().btrt_strerror(rc).decode()
+        raise BtrtError(rc, where, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Problem:
+    """The arguments of btrt_create (Eq. (1) with D = phi I), as ctypes structures.
+
+    flux_a, flux_b: B(phi) = a phi + b phi^2/2; A0 = (k11, k12, k22), beta: A = A0 (1 + beta phi^2);
+    source: None, an (ny, nx) array, or ("sin", amp, kx, ky); bc_type/bc_value for sides
+    x-, x+, y-, y+; k0; k2: "hbb" (Eq. (62)), a scalar (K2 = k2 Ihat) or four entries.
+    """
+
+    def __init__(self, nx: int, ny: int, *, precision: int = F64, flux_a=(0.0, 0.0), flux_b=(0.0, 0.0),
+                 A0=(0.0, 0.0, 0.0), beta: float = 0.0, source=None, bc_type=(PERIODIC,) * 4,
+                 bc_value=(0.0,) * 4, k0: float = 1.0, k2=1.0, check_interval: int = 1000, device: int = 0):
+        self.grid = Grid(int(nx), int(ny), int(precision), int(device), None, None, 0)
+        self.flux = Flux((ctypes.c_double * 2)(*flux_a), (ctypes.c_double * 2)(*flux_b))
+        self.diff = Diff(float(A0[0]), float(A0[1]), float(A0[2]), float(beta))
+        self.dterm = DTerm(D_PHI_I)
+        self._field = None
+        if source is None:
+            self.source = Source(SRC_NONE, 0.0, 0, 0, None)
+        elif isinstance(source, tuple) and source and source[0] == "sin":
+            _, amp, kx, ky = source
+            self.source = Source(SRC_SIN, float(amp), int(kx), int(ky), None)
+        else:
+            self._field = np.ascontiguousarray(source, dtype=np.float64).reshape(ny, nx)
+            self.source = Source(SRC_FIELD, 0.0, 0, 0, _dptr(self._field))
+        self.bc = BC((ctypes.c_int32 * 4)(*bc_type), (ctypes.c_double * 4)(*bc_value))
+        if isinstance(k2, str):
+            assert k2 == "hbb"
+            self.relax = Relax(float(k0), K2_HBB, (ctypes.c_double * 4)(0, 0, 0, 0), int(check_interval))
+        else:
+            vals = [float(k2)] * 4 if np.isscalar(k2) else [float(v) for v in k2]
+            self.relax = Relax(float(k0), K2_VALUE, (ctypes.c_double * 4)(*vals), int(check_interval))
+
+    @property
+    def nx(self) -> int:
+        return self.grid.nx
+
+    @property
+    def ny(self) -> int:
+        return self.grid.ny
+
+    def args(self):
+        b = ctypes.byref
+        return (b(self.grid), b(self.flux), b(self.diff), b(self.dterm), b(self.source), b(self.bc), b(self.relax))
+
+    def validate(self) -> Info:
+        """btrt_validate: host-side checks and derived constants; raises BtrtError."""
+        info = Info()
+        _check(lib().btrt_validate(*self.args(), ctypes.byref(info)), "btrt_validate")
+        return info
+
+    def workspace_size(self) -> int:
+        return int(lib().btrt_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.source)))
+
+
+class Solver:
+    """One btrt handle. ``torch_memory=True`` hands the library a torch-allocated workspace
+    and torch's current HIP stream; otherwise the library allocates its own."""
+
+    def __init__(self, problem: Problem, phi0: np.ndarray, torch_memory: bool = False):
+        self.problem = problem
+        self._workspace = None
+        if torch_memory:
+            import torch  # plumbing only: device memory and the stream
+
+            dev = torch.device("cuda", problem.grid.device)
+            nbytes = problem.workspace_size()
+            self._workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            problem.grid.workspace = self._workspace.data_ptr()
+            problem.grid.workspace_bytes = nbytes
+            problem.grid.stream = torch.cuda.current_stream(dev).cuda_stream
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(problem.ny, problem.nx)
+        h = ctypes.c_void_p()
+        _check(lib().btrt_create(*problem.args(), _dptr(phi0), ctypes.byref(h)), "btrt_create")
+        self.h = h
+
+    # -- calls of include/btrt.h -----------------------------------------------------------
+    def step(self, n: int) -> "Solver":
+        _check(lib().btrt_step(self.h, int(n)), "btrt_step")
+        return self
+
+    def field(self) -> np.ndarray:
+        out = np.empty((self.problem.ny, self.problem.nx), dtype=np.float64)
+        _check(lib().btrt_field(self.h, _dptr(out)), "btrt_field")
+        return out
+
+    def populations(self) -> np.ndarray:
+        out = np.empty((9, self.problem.ny, self.problem.nx), dtype=np.float64)
+        _check(lib().btrt_populations(self.h, _dptr(out)), "btrt_populations")
+        return out
+
+    def residual(self) -> float:
+        out = ctypes.c_double()
+        _check(lib().btrt_residual(self.h, ctypes.byref(out)), "btrt_residual")
+        return out.value
+
+    def error(self, ref: np.ndarray):
+        ref = np.ascontiguousarray(ref, dtype=np.float64).reshape(self.problem.ny, self.problem.nx)
+        out = np.empty(3, dtype=np.float64)
+        _check(lib().btrt_error(self.h, _dptr(ref), _dptr(out)), "btrt_error")
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def solve(self, tol: float, max_steps: int):
+        steps = ctypes.c_int64()
+        res = ctypes.c_double()
+        _check(lib().btrt_solve(self.h, float(tol), int(max_steps), ctypes.byref(steps), ctypes.byref(res)),
+               "btrt_solve")
+        return int(steps.value), float(res.value)
+
+    def sync(self) -> None:
+        _check(lib().btrt_sync(self.h), "btrt_sync")
+
+    def info(self) -> Info:
+        info = Info()
+        _check(lib().btrt_get_info(self.h, ctypes.byref(info)), "btrt_get_info")
+        return info
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _check(lib().btrt_destroy(self.h), "btrt_destroy")
+            self.h = None
+        self._workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_from_workload(w, precision: int = F64, device: int = 0, check_interval: int = 1000) -> Problem:
+    """btrt_create arguments for a workloads.Workload."""
+    return Problem(w.nx, w.ny, precision=precision, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta,
+                   source=w.source, bc_type=w.bc_type, bc_value=w.bc_value, k0=w.k0, k2=w.k2,
+                   check_interval=check_interval, device=device)

@@ -1,0 +1,72 @@
+// Internal interface between the host runtime (btrt_api.cpp) and the gfx950 kernels
+// (btrt_kernels.hip). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace btrtk {
+
+// Source kinds as the kernels see them.
+enum SrcKind : int { kSrcNone = 0, kSrcField = 1, kSrcSep = 2 };
+
+// Reduction modes of the gather kernels.
+enum ReduceMode : int { kResidual = 0, kError = 1 };
+
+// Everything one sweep needs, by value in the kernel argument segment.
+template <typename T>
+struct SweepArgs {
+    const T* fin;      // 9 planes of the post-collision populations f+(t-1)
+    T* fout;           // 9 planes receiving f+(t)
+    const T* phi_prev; // phi(t-1), one plane
+    T* phi_out;        // phi(t), one plane
+    const T* src;      // kSrcField: one plane; kSrcSep: sx[nx]
+    const T* src_y;    // kSrcSep: sy[ny]
+    int64_t plane;     // elements per plane (pitch * ny)
+    int nx, ny, pitch;
+    int perx, pery;    // 1 when the direction is periodic
+    T wall[4];         // phi_w of sides x-, x+, y-, y+
+    T ax, ay, bx, by;  // B(phi) = a phi + b phi^2 / 2
+    T a11, a12, a22, beta; // A(phi) = A0 (1 + beta phi^2), used when K1 is per node
+    T K11, K12, K22;   // K1 of Eq. (30) when A is constant
+    T k0, k2xx, k2xy, k2yy;
+    T src_amp;
+    int tiles_x, tiles_y;
+};
+
+// Gather-reduce of phi(t) (for the residual, error norms, field and population reads).
+template <typename T>
+struct GatherArgs {
+    const T* fin;      // post-collision populations f+(t-1)
+    int64_t plane;
+    int nx, ny, pitch;
+    int perx, pery;
+    T wall[4];
+    double* snap;      // kResidual: phi snapshot (dense nx*ny, FP64), updated in place
+    const double* ref; // kError: reference (dense nx*ny)
+    double* out;       // dense nx*ny output for field / population reads
+    double* partial;   // per-block partial sums (kReducePartials doubles per block)
+    int population;    // population index for the population read, -1 for phi
+};
+
+constexpr int kReducePartials = 6; // sum a, sum b, sum c, sum d, max, non-finite count
+constexpr int kReduceBlocks = 1024;
+constexpr int kBlock = 256;
+
+// Launchers (defined in btrt_kernels.hip). They return the launch's hipError_t.
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, hipStream_t s);
+template <typename T>
+hipError_t launch_init(const T* dummy, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx,
+                       int ny, int pitch, int perx, int pery, const double wall[4], double ax,
+                       double ay, double bx, double by, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_field(const GatherArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_reduce(const GatherArgs<T>& a, int mode, double* result, hipStream_t s);
+template <typename T>
+hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, hipStream_t s);
+
+}  // namespace btrtk

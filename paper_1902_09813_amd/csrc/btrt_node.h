@@ -1,0 +1,203 @@
+// Per-node pieces of the B-TriRT D2Q9 sweep (Zhao, Wu, Chai & Shi, arXiv:1902.09813):
+// the pull with half-way bounce-back (Eq. (38), Eqs. (54)-(56)) and the moment-space
+// collision (Eqs. (88), (99), (7), (8), (11)). Host-callable as well, so the same code can be
+// exercised on the CPU; the library itself only runs it inside its kernels.
+#pragma once
+
+#include "btrt_internal.h"
+
+namespace btrtk {
+
+template <typename T>
+struct Lat {
+    static constexpr T w0 = T(4) / T(9);
+    static constexpr T w1 = T(1) / T(9);
+    static constexpr T w5 = T(1) / T(36);
+};
+
+template <typename T>
+__host__ __device__ inline T wall_value(bool out_x, bool out_y, T vx, T vy)
+{
+    // A link crossing both walls (a corner point) takes the mean of the two values.
+    return (out_x && out_y) ? T(0.5) * (vx + vy) : (out_x ? vx : vy);
+}
+
+// Pull f_i(x, t) for all nine directions from the post-collision planes of t-1.
+template <typename T>
+__host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane, int x, int y, int nx,
+                                       int ny, int pitch, int perx, int pery, const T* wall, T f[9])
+{
+    const T* __restrict__ F0 = fin;
+    const T* __restrict__ F1 = fin + plane;
+    const T* __restrict__ F2 = fin + 2 * plane;
+    const T* __restrict__ F3 = fin + 3 * plane;
+    const T* __restrict__ F4 = fin + 4 * plane;
+    const T* __restrict__ F5 = fin + 5 * plane;
+    const T* __restrict__ F6 = fin + 6 * plane;
+    const T* __restrict__ F7 = fin + 7 * plane;
+    const T* __restrict__ F8 = fin + 8 * plane;
+    const int n = y * pitch + x;
+    if (x > 0 && x < nx - 1 && y > 0 && y < ny - 1) {
+        f[0] = F0[n];
+        f[1] = F1[n - 1];
+        f[2] = F2[n - pitch];
+        f[3] = F3[n + 1];
+        f[4] = F4[n + pitch];
+        f[5] = F5[n - pitch - 1];
+        f[6] = F6[n - pitch + 1];
+        f[7] = F7[n + pitch + 1];
+        f[8] = F8[n + pitch - 1];
+        return;
+    }
+    // Edge node: wrap periodic directions, bounce back at Dirichlet walls.
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool okxm = true, okxp = true, okym = true, okyp = true;
+    if (xm < 0) { if (perx) xm += nx; else okxm = false; }
+    if (xp >= nx) { if (perx) xp -= nx; else okxp = false; }
+    if (ym < 0) { if (pery) ym += ny; else okym = false; }
+    if (yp >= ny) { if (pery) yp -= ny; else okyp = false; }
+    const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
+    const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
+    f[0] = F0[n];
+    f[1] = okxm ? F1[r0 + xm] : -F3[n] + tw1 * wall[0];
+    f[2] = okym ? F2[rm + x] : -F4[n] + tw1 * wall[2];
+    f[3] = okxp ? F3[r0 + xp] : -F1[n] + tw1 * wall[1];
+    f[4] = okyp ? F4[rp + x] : -F2[n] + tw1 * wall[3];
+    f[5] = (okxm && okym) ? F5[rm + xm] : -F7[n] + tw5 * wall_value(!okxm, !okym, wall[0], wall[2]);
+    f[6] = (okxp && okym) ? F6[rm + xp] : -F8[n] + tw5 * wall_value(!okxp, !okym, wall[1], wall[2]);
+    f[7] = (okxp && okyp) ? F7[rp + xp] : -F5[n] + tw5 * wall_value(!okxp, !okyp, wall[1], wall[3]);
+    f[8] = (okxm && okyp) ? F8[rp + xm] : -F6[n] + tw5 * wall_value(!okxm, !okyp, wall[0], wall[3]);
+}
+
+template <typename T>
+__host__ __device__ inline T sum9(const T f[9])
+{
+    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+// One node of the B-TriRT collision in moment space; f holds f(x, t) on entry and
+// f+(x, t) on return. Returns phi(t).
+template <typename T, int SRC, bool KPHI>
+__host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, T s)
+{
+    constexpr T third = T(1) / T(3);
+    constexpr T sixth = T(1) / T(6);
+    constexpr T twelfth = T(1) / T(12);
+    constexpr T ninth = T(1) / T(9);
+
+    // Moments m = T f, rows of Eq. (88).
+    const T phi = sum9(f);
+    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T sd = (f[5] + f[6]) + (f[7] + f[8]);
+    const T pxx = (f[1] + f[3]) + sd;
+    const T pyy = (f[2] + f[4]) + sd;
+    const T pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const T m6 = ((f[5] + f[6]) - (f[7] + f[8])) - third * jy;
+    const T m7 = ((f[5] + f[8]) - (f[6] + f[7])) - third * jx;
+    const T m8 = sd - third * (pxx + pyy);
+
+    // Flux B(phi) and its backward difference over one step (correction G, Eq. (11)).
+    const T Bx = phi * (a.ax + T(0.5) * a.bx * phi);
+    const T By = phi * (a.ay + T(0.5) * a.by * phi);
+    const T dBx = Bx - phi_prev * (a.ax + T(0.5) * a.bx * phi_prev);
+    const T dBy = By - phi_prev * (a.ay + T(0.5) * a.by * phi_prev);
+
+    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)).
+    T K11 = a.K11, K12 = a.K12, K22 = a.K22;
+    if constexpr (KPHI) {
+        const T g = T(1) + a.beta * phi * phi;
+        const T m11 = T(3) * a.a11 * g + T(0.5);
+        const T m12 = T(3) * a.a12 * g;
+        const T m22 = T(3) * a.a22 * g + T(0.5);
+        const T rdet = T(1) / (m11 * m22 - m12 * m12);
+        K11 = m22 * rdet;
+        K12 = -m12 * rdet;
+        K22 = m11 * rdet;
+    }
+
+    // Block relaxation (Eq. (99)) towards the equilibrium moments of Eq. (7) with D = phi I:
+    // (phi, B, phi/3, 0, phi/3, 0, 0, -phi/9); source s (Eq. (8)) enters as s (1, 0, 0, 1/3, 0,
+    // 1/3, 0, 0, -1/9); G adds (I - K1/2) dB to j.
+    const T ex = jx - Bx, ey = jy - By;
+    const T jxp = jx - (K11 * ex + K12 * ey) + dBx - T(0.5) * (K11 * dBx + K12 * dBy);
+    const T jyp = jy - (K12 * ex + K22 * ey) + dBy - T(0.5) * (K12 * dBx + K22 * dBy);
+    const T phi3 = third * phi;
+    const T s3 = third * s;
+    const T pxxp = pxx - a.k2xx * (pxx - phi3) + s3;
+    const T pyyp = pyy - a.k2yy * (pyy - phi3) + s3;
+    const T pxyp = (T(1) - a.k2xy) * pxy;
+    const T om0 = T(1) - a.k0;
+    const T m6p = om0 * m6;
+    const T m7p = om0 * m7;
+    const T m8p = m8 - a.k0 * (m8 + ninth * phi) - ninth * s;
+    const T phip = phi + s;
+
+    // f+ = T^-1 m+ (dual basis of the rows of T).
+    f[0] = phip - T(2) * third * (pxxp + pyyp) + m8p;
+    const T c13 = third * pxxp - sixth * pyyp - T(0.5) * m8p;
+    const T d13 = third * jxp - T(0.5) * m7p;
+    f[1] = c13 + d13;
+    f[3] = c13 - d13;
+    const T c24 = third * pyyp - sixth * pxxp - T(0.5) * m8p;
+    const T d24 = third * jyp - T(0.5) * m6p;
+    f[2] = c24 + d24;
+    f[4] = c24 - d24;
+    const T e = twelfth * (pxxp + pyyp) + T(0.25) * m8p;
+    const T h57 = e + T(0.25) * pxyp;
+    const T g57 = twelfth * (jxp + jyp) + T(0.25) * (m6p + m7p);
+    f[5] = h57 + g57;
+    f[7] = h57 - g57;
+    const T h68 = e - T(0.25) * pxyp;
+    const T g68 = twelfth * (jyp - jxp) + T(0.25) * (m6p - m7p);
+    f[6] = h68 + g68;
+    f[8] = h68 - g68;
+    return phi;
+}
+
+
+// f+(-1) at node (x, y) such that the first pull yields f(0) = f^eq(phi0) (Section 4): a value
+// whose consumer is an interior pull gets f^eq of Eq. (7) (D = phi I) at its destination; a
+// value whose consumer is the bounce-back rule gets 2 w phi_w - f^eq_opp at its own node.
+// Also phi(-1) := phi0, so the correction G starts at zero.
+template <typename T>
+__host__ __device__ inline void init_node(T* __restrict__ f, T* __restrict__ phi_prev,
+                                          const double* __restrict__ phi0, int64_t plane, int x, int y, int nx,
+                                          int ny, int pitch, int perx, int pery, const double wall[4], double ax,
+                                          double ay, double bx, double by)
+{
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const double wt[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const int64_t k = static_cast<int64_t>(y) * nx + x;
+    const double here = phi0[k];
+    const int n = y * pitch + x;
+    for (int i = 0; i < 9; ++i) {
+        int xd = x + cx[i], yd = y + cy[i];
+        bool outx = false, outy = false;
+        if (xd < 0) { if (perx) xd += nx; else outx = true; }
+        if (xd >= nx) { if (perx) xd -= nx; else outx = true; }
+        if (yd < 0) { if (pery) yd += ny; else outy = true; }
+        if (yd >= ny) { if (pery) yd -= ny; else outy = true; }
+        double v;
+        if (!outx && !outy) {
+            const double p = phi0[static_cast<int64_t>(yd) * nx + xd];
+            const double Bx = p * (ax + 0.5 * bx * p), By = p * (ay + 0.5 * by * p);
+            v = wt[i] * (p + 3.0 * (cx[i] * Bx + cy[i] * By));
+        } else {
+            // The link leaves through x- or x+ (y- or y+) according to the sign of c_i.
+            const double vx = wall[cx[i] < 0 ? 0 : 1];
+            const double vy = wall[cy[i] < 0 ? 2 : 3];
+            const double pw = (outx && outy) ? 0.5 * (vx + vy) : (outx ? vx : vy);
+            const int o = opp[i];
+            const double Bx = here * (ax + 0.5 * bx * here), By = here * (ay + 0.5 * by * here);
+            const double feq_o = wt[o] * (here + 3.0 * (cx[o] * Bx + cy[o] * By));
+            v = 2.0 * wt[i] * pw - feq_o;
+        }
+        f[i * plane + n] = static_cast<T>(v);
+    }
+    phi_prev[n] = static_cast<T>(here);
+}
+
+}  // namespace btrtk

@@ -1,0 +1,107 @@
+"""Seeded synthetic workloads (problem parameters and initial fields), in lattice units.
+
+This module holds inputs only: parameters and initial fields drawn from fixed seeds.
+It contains none of the method's arithmetic, so the HIP path and the CPU oracle can
+both take their inputs from here without sharing any computation.
+
+Workloads (lattice units; the paper's problems are analytic, so no dataset is involved):
+
+* ``c1``  64 x 64 periodic, A = 0.01 I, B = phi (0.05, 0.05), S = 0, phi0 a periodised
+          Gaussian hill (sigma 6, centre at the box centre), 2000 steps. k2 from the
+          bounce-back rule (Eq. (62)) or k2 = 1.
+* ``c2``  1024 x 1024, Dirichlet phi_w = 0 on all sides, A = [[0.02, 0.008], [0.008, 0.01]],
+          B = phi (0.02, 0), S = sin(pi x / L) sin(pi y / L), phi0 ~ U[0, 1) (seed 2),
+          k0 = k2 = 1, 20000 steps.
+* ``c3``  4096 x 4096 periodic, B = 0.025 phi^2 (1, 1), A(phi) = diag(0.01, 0.005)(1 + phi^2),
+          S = 0, phi0 = sum of 16 Gaussians (seed 3; amplitude U[0, 1], sigma U[8, 64], centre
+          U[0, 4096)^2, minimum-image distance), k0 = k2 = 1, 5000 steps.
+
+``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
+sizes; ragged sizes exercise partial tiles).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+PERIODIC, DIRICHLET = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    steps: int
+    flux_a: Tuple[float, float] = (0.0, 0.0)
+    flux_b: Tuple[float, float] = (0.0, 0.0)
+    A0: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    beta: float = 0.0
+    source: Optional[tuple] = None          # None or ("sin", amp, kx, ky)
+    bc_type: Tuple[int, int, int, int] = (PERIODIC,) * 4
+    bc_value: Tuple[float, float, float, float] = (0.0,) * 4
+    k0: float = 1.0
+    k2: object = 1.0                        # scalar, 4 entries, or "hbb" (Eq. (62))
+    seed: int = 0
+    phi0_kind: str = "uniform"
+    extra: dict = field(default_factory=dict)
+
+    def phi0(self) -> np.ndarray:
+        return initial_field(self)
+
+    def scaled(self, nx: int, ny: int, steps: Optional[int] = None) -> "Workload":
+        return replace(self, nx=nx, ny=ny, steps=self.steps if steps is None else steps)
+
+
+def c1(k2="hbb") -> Workload:
+    return Workload("c1_gaussian_64_periodic", 64, 64, 2000, flux_a=(0.05, 0.05), A0=(0.01, 0.0, 0.01),
+                    k0=1.0, k2=k2, phi0_kind="hill", extra={"sigma": 6.0})
+
+
+def c2() -> Workload:
+    return Workload("c2_aniso_1024_hbb", 1024, 1024, 20000, flux_a=(0.02, 0.0), A0=(0.02, 0.008, 0.01),
+                    source=("sin", 1.0, 1, 1), bc_type=(DIRICHLET,) * 4, bc_value=(0.0,) * 4, k0=1.0, k2=1.0,
+                    seed=2, phi0_kind="uniform")
+
+
+def c3() -> Workload:
+    return Workload("c3_nonlinear_4096_periodic", 4096, 4096, 5000, flux_b=(0.05, 0.05), A0=(0.01, 0.0, 0.005),
+                    beta=1.0, k0=1.0, k2=1.0, seed=3, phi0_kind="gaussians", extra={"count": 16})
+
+
+def initial_field(w: Workload) -> np.ndarray:
+    """phi0 on the cell-centred nodes (i + 1/2, j + 1/2), shape (ny, nx)."""
+    x = np.arange(w.nx, dtype=np.float64) + 0.5
+    y = np.arange(w.ny, dtype=np.float64) + 0.5
+    X, Y = np.meshgrid(x, y)
+    if w.phi0_kind == "uniform":
+        return np.random.default_rng(w.seed).random((w.ny, w.nx))
+    if w.phi0_kind == "hill":
+        # Gaussian of unit peak at the box centre, summed over periodic images |m|,|n| <= 2.
+        s = w.extra["sigma"]
+        cx, cy = w.nx / 2.0, w.ny / 2.0
+        out = np.zeros((w.ny, w.nx))
+        for m in range(-2, 3):
+            for n in range(-2, 3):
+                out += np.exp(-((X - cx - m * w.nx) ** 2 + (Y - cy - n * w.ny) ** 2) / (2.0 * s * s))
+        return out
+    if w.phi0_kind == "gaussians":
+        rng = np.random.default_rng(w.seed)
+        k = w.extra["count"]
+        amp = rng.uniform(0.0, 1.0, k)
+        sig = rng.uniform(8.0, 64.0, k)
+        # Centres scale with the box so scaled variants keep the same layout.
+        cx = rng.uniform(0.0, 1.0, k) * w.nx
+        cy = rng.uniform(0.0, 1.0, k) * w.ny
+        sig = sig * max(min(w.nx, w.ny) / 4096.0, 0.125) if min(w.nx, w.ny) < 4096 else sig
+        out = np.zeros((w.ny, w.nx))
+        for a, s, x0, y0 in zip(amp, sig, cx, cy):
+            dx = X - x0
+            dx -= w.nx * np.round(dx / w.nx)
+            dy = Y - y0
+            dy -= w.ny * np.round(dy / w.ny)
+            out += a * np.exp(-(dx * dx + dy * dy) / (2.0 * s * s))
+        return out
+    raise ValueError(w.phi0_kind)
