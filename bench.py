@@ -34,14 +34,26 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def timed_run(w, precision, steps, warmup):
+def sweep_launches(steps, fusion):
+    """Sweep launches btrt_step makes for ``steps`` steps, chunked at every residual check."""
+    n = 0
+    done = 0
+    while done < steps:
+        k = min(CHECK_INTERVAL, steps - done)
+        n += k // fusion + k % fusion
+        done += k
+    return n
+
+
+def timed_run(w, precision, steps, warmup, fusion=2):
     """Warm up, then time exactly ``steps`` steps with HIP events on the library's stream."""
     import torch
     from paper_1902_09813_amd import btrt
 
     prob = btrt.problem_from_workload(w, precision=precision, check_interval=CHECK_INTERVAL)
-    solver = btrt.Solver(prob, w.phi0(), torch_memory=True)  # torch memory + torch's current stream
-    stream = torch.cuda.current_stream()
+    solver = btrt.Solver(prob, w.phi0(), torch_memory=True)  # torch memory + a torch stream
+    solver.set_fusion(fusion)
+    stream = solver.torch_stream  # the stream every kernel of the solver is launched on
     info = solver.info()
     solver.step(warmup)
     solver.sync()
@@ -78,9 +90,10 @@ def timed_run(w, precision, steps, warmup):
         "ms_total": total_ms,
         "wall_s": wall,
         "ms_per_step": total_ms / steps,
-        "sweep_ms_avg": sweep_ms / steps,
+        "launches": sweep_launches(steps, fusion),
+        "launch_ms_avg": sweep_ms / sweep_launches(steps, fusion),
         "mlups": nodes * steps / (total_ms * 1e-3) / 1e6,
-        "bytes_per_update": info.bytes_per_update,
+        "bytes_per_node_launch": info.bytes_per_node_launch,
         "nodes": nodes,
         "residual": residual,
     }
@@ -108,7 +121,7 @@ def cpu_baseline(w, budget_s=15.0):
     }
 
 
-def traffic_for(precision_name, nodes):
+def traffic_for(precision_name, nodes, fusion):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None if the
     kernel source changed since the counters were taken."""
     try:
@@ -118,7 +131,7 @@ def traffic_for(precision_name, nodes):
         return None
     if rec.get("kernel_sha256_16") != kernel_hash():
         return None
-    ent = rec.get(precision_name)
+    ent = rec.get(f"{precision_name}_fusion{fusion}")
     if not ent or ent.get("nodes") != nodes:
         return None
     return ent.get("bytes_per_launch")
@@ -142,6 +155,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--fusion", type=int, choices=[1, 2], default=2, help="time steps per sweep launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
@@ -169,34 +183,39 @@ def main():
     w = W.c3()
     print(f"[bench] {w.name} {args.precision}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
           flush=True)
-    r = timed_run(w, prec, args.steps, args.warmup)
-    bytes_per_launch = r["bytes_per_update"] * r["nodes"]
-    achieved = bytes_per_launch / (r["sweep_ms_avg"] * 1e-3) / 1e9
+    r = timed_run(w, prec, args.steps, args.warmup, args.fusion)
+    bytes_per_launch = r["bytes_per_node_launch"] * r["nodes"]
+    achieved = bytes_per_launch / (r["launch_ms_avg"] * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": "sweep_kernel",
+        "kernel": "sweep2_kernel" if args.fusion == 2 else "sweep_kernel",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(args.precision, r["nodes"]),
+        "traffic": traffic_for(args.precision, r["nodes"], args.fusion),
         "bytes_per_launch": bytes_per_launch,
-        "sweep_ms_avg": round(r["sweep_ms_avg"], 5),
+        "steps_per_launch": args.fusion,
+        "launch_us_avg": round(r["launch_ms_avg"] * 1e3, 2),
     }
     extra = {}
     if not args.no_extra:
         other = btrt.F32 if prec == btrt.F64 else btrt.F64
         name = "f32" if other == btrt.F32 else "f64"
         print(f"[bench] side measurement: {w.name} {name}", file=sys.stderr, flush=True)
-        r2 = timed_run(w, other, min(args.steps, 2000), 50)
+        r2 = timed_run(w, other, min(args.steps, 2000), 50, args.fusion)
         extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
-        extra[f"c3_{name}_hbm_frac"] = round(r2["bytes_per_update"] * r2["nodes"] / (r2["sweep_ms_avg"] * 1e-3)
+        extra[f"c3_{name}_hbm_frac"] = round(r2["bytes_per_node_launch"] * r2["nodes"] / (r2["launch_ms_avg"] * 1e-3)
                                              / 1e9 / HBM_PEAK_GBS, 4)
+        r1 = timed_run(w, prec, min(args.steps, 1000), 20, 1)
+        extra[f"c3_{args.precision}_one_step_per_launch_mlups"] = round(r1["mlups"], 1)
+        extra[f"c3_{args.precision}_one_step_per_launch_hbm_frac"] = round(
+            r1["bytes_per_node_launch"] * r1["nodes"] / (r1["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         w2 = W.c2()
         print(f"[bench] side measurement: {w2.name} f64", file=sys.stderr, flush=True)
-        r3 = timed_run(w2, btrt.F64, 2000, 50)
+        r3 = timed_run(w2, btrt.F64, 2000, 50, args.fusion)
         extra["c2_f64_mlups"] = round(r3["mlups"], 1)
-        extra["c2_f64_sweep_us"] = round(r3["sweep_ms_avg"] * 1e3, 2)
+        extra["c2_f64_launch_us"] = round(r3["launch_ms_avg"] * 1e3, 2)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

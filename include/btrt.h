@@ -127,7 +127,9 @@ typedef struct {
     double K2[4];                     /* resolved K2 */
     double k0;
     size_t workspace_bytes;           /* device bytes a handle needs */
-    double bytes_per_update;          /* algorithmic HBM bytes of one node update */
+    double bytes_per_node_launch;     /* algorithmic HBM bytes per node and sweep launch: the
+                                         state read once and written once (9 populations +
+                                         phi each way), whether the launch fuses 1 or 2 steps */
     int64_t step;                     /* steps taken (btrt_get_info only) */
 } btrt_info_t;
 
@@ -156,6 +158,11 @@ int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t
 /* Enqueues n >= 0 time steps (collide, stream, bounce back) on the handle's stream and
  * returns without waiting. */
 int btrt_step(btrt_t* h, int64_t n);
+
+/* Time steps fused into one kernel launch by btrt_step: 2 (the default) runs two steps per
+ * launch through an on-chip tile, halving HBM traffic per step; 1 runs one step per launch.
+ * Both give bitwise identical results. Errors: BTRT_E_INVAL for other values. */
+int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch);
 
 /* phi(t) = sum_i f_i(x, t) (Eq. (9)) into phi_out[nx*ny]. Synchronises. */
 int btrt_field(btrt_t* h, double* phi_out);

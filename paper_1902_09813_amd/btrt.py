@@ -24,7 +24,7 @@ D_PHI_I = 0
 K2_VALUE, K2_HBB = 0, 1
 
 # Every function include/btrt.h declares.
-EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_field",
+EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_fusion", "btrt_field",
            "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
            "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error")
 
@@ -66,7 +66,7 @@ class Info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("pitch", ctypes.c_int32), ("k1_per_node", ctypes.c_int32), ("K1", ctypes.c_double * 4),
                 ("K2", ctypes.c_double * 4), ("k0", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
-                ("bytes_per_update", ctypes.c_double), ("step", ctypes.c_int64)]
+                ("bytes_per_node_launch", ctypes.c_double), ("step", ctypes.c_int64)]
 
 
 class BtrtError(RuntimeError):
@@ -85,6 +85,14 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                               "python paper_1902_09813_amd/build.py")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname). Loading
+        # torch first makes libbtrt bind to that copy, so device pointers and streams handed
+        # over from torch belong to the runtime the library launches on. Without torch the
+        # system runtime is used.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
@@ -94,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "btrt_workspace_size": ([P(Grid), P(Source)], ctypes.c_size_t),
             "btrt_create": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, P(hp)], ctypes.c_int),
             "btrt_step": ([hp, ctypes.c_int64], ctypes.c_int),
+            "btrt_set_fusion": ([hp, ctypes.c_int32], ctypes.c_int),
             "btrt_field": ([hp, dp], ctypes.c_int),
             "btrt_populations": ([hp, dp], ctypes.c_int),
             "btrt_residual": ([hp, dp], ctypes.c_int),
@@ -184,6 +193,7 @@ class Solver:
     def __init__(self, problem: Problem, phi0: np.ndarray, torch_memory: bool = False):
         self.problem = problem
         self._workspace = None
+        self.torch_stream = None
         if torch_memory:
             import torch  # plumbing only: device memory and the stream
 
@@ -192,7 +202,13 @@ class Solver:
             self._workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
             problem.grid.workspace = self._workspace.data_ptr()
             problem.grid.workspace_bytes = nbytes
-            problem.grid.stream = torch.cuda.current_stream(dev).cuda_stream
+            # torch's current stream, or a torch stream of default priority when that is the
+            # legacy null stream (a NULL handle would make the library create its own).
+            stream = torch.cuda.current_stream(dev)
+            if stream.cuda_stream == 0:
+                stream = torch.cuda.Stream(dev)
+            self.torch_stream = stream
+            problem.grid.stream = stream.cuda_stream
         phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(problem.ny, problem.nx)
         h = ctypes.c_void_p()
         _check(lib().btrt_create(*problem.args(), _dptr(phi0), ctypes.byref(h)), "btrt_create")
@@ -201,6 +217,10 @@ class Solver:
     # -- calls of include/btrt.h -----------------------------------------------------------
     def step(self, n: int) -> "Solver":
         _check(lib().btrt_step(self.h, int(n)), "btrt_step")
+        return self
+
+    def set_fusion(self, steps_per_launch: int) -> "Solver":
+        _check(lib().btrt_set_fusion(self.h, int(steps_per_launch)), "btrt_set_fusion")
         return self
 
     def field(self) -> np.ndarray:

@@ -18,6 +18,9 @@ FLAGS = [
     "-shared",
     # Keep the compiler from forming packed FP32 instructions.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # No implicit multiply-add contraction: the kernels write every FMA explicitly, so a node
+    # update rounds identically in every kernel (one-step, two-step) and on the host.
+    "-ffp-contract=off",
     "-Wall",
     "-I" + os.path.join(ROOT, "include"),
     "-I" + CSRC,

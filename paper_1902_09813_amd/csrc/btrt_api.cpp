@@ -195,7 +195,7 @@ void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_
     info->workspace_bytes = layout_for(g->nx, g->ny, g->precision, src_kind).total;
     // 9 population reads + 9 writes + phi(t-1) read + phi(t) write, plus a per-node source.
     const double es = g->precision == BTRT_F64 ? 8.0 : 4.0;
-    info->bytes_per_update = (20.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * es;
+    info->bytes_per_node_launch = (20.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * es;
     info->step = 0;
 }
 
@@ -214,6 +214,7 @@ struct btrt {
     int64_t step = 0;
     int check_interval = 1000;
     bool k1_per_node = false;
+    int fuse = 2;       // time steps fused per launch (1 or 2)
     btrt_info_t info{};
     SweepArgs<double> a64{};
     SweepArgs<float> a32{};
@@ -252,8 +253,9 @@ void fill_sweep(btrt* h, SweepArgs<T>& a, const btrt_flux_t* B, const btrt_diff_
     a.src_amp = static_cast<T>(R && R->kind == BTRT_SRC_SIN ? R->amp : 0.0);
     a.src = h->src_kind == kSrcNone ? nullptr : reinterpret_cast<const T*>(h->mem + h->L.src);
     a.src_y = h->src_kind == kSrcSep ? reinterpret_cast<const T*>(h->mem + h->L.src_y) : nullptr;
-    a.tiles_x = (h->nx + 63) / 64;
-    a.tiles_y = (h->ny + 3) / 4;
+    // Non-temporal stores once the two population buffers exceed the 256 MB Infinity Cache.
+    const double state_bytes = 2.0 * 10.0 * static_cast<double>(h->plane) * sizeof(T);
+    a.nts = state_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
 }
 
 template <typename T>
@@ -335,7 +337,8 @@ int gather_dense(btrt* h, int population, double* host_out)
 
 int enqueue_steps(btrt* h, int64_t n)
 {
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n;) {
+        const int k = (h->fuse >= 2 && n - i >= 2) ? 2 : 1;  // time steps in this launch
         const int nxt = h->cur ^ 1;
         hipError_t e;
         if (h->precision == BTRT_F64) {
@@ -344,18 +347,19 @@ int enqueue_steps(btrt* h, int64_t n)
             a.fout = reinterpret_cast<double*>(h->mem + h->L.f[nxt]);
             a.phi_prev = reinterpret_cast<const double*>(h->mem + h->L.phi[h->cur]);
             a.phi_out = reinterpret_cast<double*>(h->mem + h->L.phi[nxt]);
-            e = launch_sweep<double>(a, h->src_kind, h->k1_per_node, h->stream);
+            e = launch_sweep<double>(a, h->src_kind, h->k1_per_node, k, h->stream);
         } else {
             SweepArgs<float>& a = h->a32;
             a.fin = reinterpret_cast<const float*>(h->mem + h->L.f[h->cur]);
             a.fout = reinterpret_cast<float*>(h->mem + h->L.f[nxt]);
             a.phi_prev = reinterpret_cast<const float*>(h->mem + h->L.phi[h->cur]);
             a.phi_out = reinterpret_cast<float*>(h->mem + h->L.phi[nxt]);
-            e = launch_sweep<float>(a, h->src_kind, h->k1_per_node, h->stream);
+            e = launch_sweep<float>(a, h->src_kind, h->k1_per_node, k, h->stream);
         }
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
         h->cur = nxt;
-        ++h->step;
+        h->step += k;
+        i += k;
     }
     return BTRT_OK;
 }
@@ -535,6 +539,15 @@ int btrt_step(btrt_t* h, int64_t n)
     if (n < 0) return fail(BTRT_E_INVAL, "n = %lld < 0", static_cast<long long>(n));
     int rc = on_device(h, [&]() { return enqueue_steps(h, n); });
     return rc == BTRT_OK ? ok() : rc;
+}
+
+int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return fail(BTRT_E_INVAL, "steps_per_launch = %d: must be 1 or 2", steps_per_launch);
+    h->fuse = steps_per_launch;
+    return ok();
 }
 
 int btrt_field(btrt_t* h, double* phi_out)

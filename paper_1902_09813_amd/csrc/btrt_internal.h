@@ -33,7 +33,8 @@ struct SweepArgs {
     T K11, K12, K22;   // K1 of Eq. (30) when A is constant
     T k0, k2xx, k2xy, k2yy;
     T src_amp;
-    int tiles_x, tiles_y;
+    int tiles_x, tiles_y; // set by the launcher for the kernel it picks
+    int nts;              // 1: non-temporal stores (grids much larger than the caches)
 };
 
 // Gather-reduce of phi(t) (for the residual, error norms, field and population reads).
@@ -56,8 +57,9 @@ constexpr int kReduceBlocks = 1024;
 constexpr int kBlock = 256;
 
 // Launchers (defined in btrt_kernels.hip). They return the launch's hipError_t.
+// steps: 1 (one time step) or 2 (two fused time steps through LDS).
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, int steps, hipStream_t s);
 template <typename T>
 hipError_t launch_init(const T* dummy, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx,
                        int ny, int pitch, int perx, int pery, const double wall[4], double ax,

@@ -37,6 +37,26 @@ __device__ __forceinline__ int xcd_tile()
     return k * q + (k < r ? k : r) + j;
 }
 
+template <typename T>
+__device__ __forceinline__ void store(T* p, T v, bool nontemporal)
+{
+    // Non-temporal stores keep a grid much larger than the caches from evicting the data
+    // the next tiles are about to pull; small grids keep them cached (they fit in the MALL).
+    if (nontemporal)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <typename T, int SRC>
+__device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int y)
+{
+    if constexpr (SRC == kSrcField) return a.src[n];
+    if constexpr (SRC == kSrcSep) return a.src_amp * a.src[x] * a.src_y[y];
+    return T(0);
+}
+
+// One time step, one thread per node (tile kTileX x kTileY).
 template <typename T, int SRC, bool KPHI>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
 {
@@ -50,18 +70,116 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
     T f[9];
     gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
     const int n = y * a.pitch + x;
-    const T phi_prev = a.phi_prev[n];
-    T s = T(0);
-    if constexpr (SRC == kSrcField) s = a.src[n];
-    if constexpr (SRC == kSrcSep) s = a.src_amp * a.src[x] * a.src_y[y];
-
-    const T phi = collide<T, SRC, KPHI>(a, f, phi_prev, s);
-
-    T* __restrict__ o = a.fout;
+    const T phi = collide<T, SRC, KPHI>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y));
     const int64_t p = a.plane;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o[i * p + n] = f[i];
-    a.phi_out[n] = phi;
+    for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, f[i], a.nts);
+    store(a.phi_out + n, phi, a.nts);
+}
+
+// Wrap a coordinate of a periodic direction into [0, n) (any distance).
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Two time steps per launch over a kTile2X x TY2 tile. Step 1 runs on the tile plus a
+// one-node ring, pulling f+(t-1) from global memory, and leaves f+(t) and phi(t) in LDS;
+// step 2 runs on the tile, pulling f+(t) from LDS (bounce-back at Dirichlet walls uses the
+// node's own LDS values), and stores f+(t+1) and phi(t+1). Every node update is the same
+// gather/collide arithmetic as in sweep_kernel, so results are bitwise identical to two
+// single steps; HBM traffic per node update is halved.
+constexpr int kTile2X = 64;
+constexpr int kBlock2 = 512;
+
+template <typename T>
+struct Tile2 {
+    static constexpr int TY = sizeof(T) == 8 ? 8 : 16;  // LDS: FP64 52.8 KB, FP32 47.5 KB
+    static constexpr int EX = kTile2X + 2, EY = TY + 2, E = EX * EY;
+    static constexpr int S1 = (E + kBlock2 - 1) / kBlock2;
+    static constexpr int S2 = (kTile2X * TY + kBlock2 - 1) / kBlock2;
+};
+
+template <typename T, int SRC, bool KPHI>
+__global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<T> a)
+{
+    using G = Tile2<T>;
+    constexpr int TX = kTile2X, TY = G::TY, EX = G::EX, E = G::E;
+    __shared__ T lf[9][E];
+    __shared__ T lphi[E];
+    const int tile = xcd_tile();
+    const int ty = tile / a.tiles_x;
+    const int tx = tile - ty * a.tiles_x;
+    const int nx = a.nx, ny = a.ny;
+    const int x0 = tx * TX - 1, y0 = ty * TY - 1;  // global position of LDS slot (0, 0)
+
+    // Step 1 on the extended tile; all loads are issued before any collision.
+    T f[G::S1][9];
+    T pp[G::S1];
+    int gxs[G::S1], gys[G::S1];
+    bool live[G::S1];
+#pragma unroll
+    for (int j = 0; j < G::S1; ++j) {
+        const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
+        const int ly = s / EX, lx = s - ly * EX;
+        int gx = x0 + lx, gy = y0 + ly;
+        bool e = s < E;
+        if (gx < 0 || gx >= nx) {
+            if (a.perx) gx = wrap(gx, nx); else e = false;
+        }
+        if (gy < 0 || gy >= ny) {
+            if (a.pery) gy = wrap(gy, ny); else e = false;
+        }
+        live[j] = e;
+        gxs[j] = gx;
+        gys[j] = gy;
+        if (e) {
+            gather(a.fin, a.plane, gx, gy, nx, ny, a.pitch, a.perx, a.pery, a.wall, f[j]);
+            pp[j] = a.phi_prev[gy * a.pitch + gx];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < G::S1; ++j) {
+        if (!live[j]) continue;
+        const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
+        const int n = gys[j] * a.pitch + gxs[j];
+        const T phi = collide<T, SRC, KPHI>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j]));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lf[i][s] = f[j][i];
+        lphi[s] = phi;
+    }
+    __syncthreads();
+
+    // Step 2 on the tile, pulling from LDS.
+    const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
+#pragma unroll
+    for (int j = 0; j < G::S2; ++j) {
+        const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
+        if (s >= TX * TY) continue;
+        const int iy = s / TX, ix = s - iy * TX;
+        const int gx = tx * TX + ix, gy = ty * TY + iy;
+        if (gx >= nx || gy >= ny) continue;
+        const int l = (iy + 1) * EX + ix + 1;
+        const bool okxm = a.perx || gx > 0, okxp = a.perx || gx < nx - 1;
+        const bool okym = a.pery || gy > 0, okyp = a.pery || gy < ny - 1;
+        T g[9];
+        g[0] = lf[0][l];
+        g[1] = okxm ? lf[1][l - 1] : bounce(lf[3][l], tw1, a.wall[0]);
+        g[2] = okym ? lf[2][l - EX] : bounce(lf[4][l], tw1, a.wall[2]);
+        g[3] = okxp ? lf[3][l + 1] : bounce(lf[1][l], tw1, a.wall[1]);
+        g[4] = okyp ? lf[4][l + EX] : bounce(lf[2][l], tw1, a.wall[3]);
+        g[5] = (okxm && okym) ? lf[5][l - EX - 1] : bounce(lf[7][l], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
+        g[6] = (okxp && okym) ? lf[6][l - EX + 1] : bounce(lf[8][l], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
+        g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
+        g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+        const int n = gy * a.pitch + gx;
+        const T phi = collide<T, SRC, KPHI>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy));
+        const int64_t p = a.plane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, g[i], a.nts);
+        store(a.phi_out + n, phi, a.nts);
+    }
 }
 
 // f+(-1) such that the first pull yields f(0) = f^eq(phi0) (Section 4 initialisation).
@@ -197,10 +315,25 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock
 }  // namespace
 
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs<T>& a_in, int src_kind, bool k1_per_node, int steps, hipStream_t s)
 {
-    const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
-#define BTRT_SWEEP(SRC, KP) hipLaunchKernelGGL((sweep_kernel<T, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a)
+    SweepArgs<T> a = a_in;
+    unsigned grid;
+    if (steps == 2) {
+        a.tiles_x = (a.nx + kTile2X - 1) / kTile2X;
+        a.tiles_y = (a.ny + Tile2<T>::TY - 1) / Tile2<T>::TY;
+    } else {
+        a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+        a.tiles_y = (a.ny + kTileY - 1) / kTileY;
+    }
+    grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
+#define BTRT_SWEEP(SRC, KP)                                                                                \
+    do {                                                                                                   \
+        if (steps == 2)                                                                                    \
+            hipLaunchKernelGGL((sweep2_kernel<T, SRC, KP>), dim3(grid), dim3(kBlock2), 0, s, a);          \
+        else                                                                                               \
+            hipLaunchKernelGGL((sweep_kernel<T, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);            \
+    } while (0)
     if (k1_per_node) {
         if (src_kind == kSrcField) BTRT_SWEEP(kSrcField, true);
         else if (src_kind == kSrcSep) BTRT_SWEEP(kSrcSep, true);
@@ -257,7 +390,7 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
 }
 
 #define BTRT_INSTANTIATE(T)                                                                                  \
-    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, bool, hipStream_t);                       \
+    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, bool, int, hipStream_t);                  \
     template hipError_t launch_init<T>(const T*, T*, T*, const double*, int64_t, int, int, int, int, int,    \
                                        const double[4], double, double, double, double, hipStream_t);        \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, hipStream_t);                          \

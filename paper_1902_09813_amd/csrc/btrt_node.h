@@ -8,6 +8,23 @@
 
 namespace btrtk {
 
+// a*b + c with a single rounding, in the storage type.
+template <typename T>
+__host__ __device__ inline T fmadd(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4)
+        return fmaf(a, b, c);
+    else
+        return fma(a, b, c);
+}
+
+// Half-way bounce-back value (Eqs. (54)-(56)): -f_opp+ + 2 w phi_w.
+template <typename T>
+__host__ __device__ inline T bounce(T f_opp, T two_w, T phi_w)
+{
+    return fmadd(two_w, phi_w, -f_opp);
+}
+
 template <typename T>
 struct Lat {
     static constexpr T w0 = T(4) / T(9);
@@ -59,14 +76,14 @@ __host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane,
     const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
     f[0] = F0[n];
-    f[1] = okxm ? F1[r0 + xm] : -F3[n] + tw1 * wall[0];
-    f[2] = okym ? F2[rm + x] : -F4[n] + tw1 * wall[2];
-    f[3] = okxp ? F3[r0 + xp] : -F1[n] + tw1 * wall[1];
-    f[4] = okyp ? F4[rp + x] : -F2[n] + tw1 * wall[3];
-    f[5] = (okxm && okym) ? F5[rm + xm] : -F7[n] + tw5 * wall_value(!okxm, !okym, wall[0], wall[2]);
-    f[6] = (okxp && okym) ? F6[rm + xp] : -F8[n] + tw5 * wall_value(!okxp, !okym, wall[1], wall[2]);
-    f[7] = (okxp && okyp) ? F7[rp + xp] : -F5[n] + tw5 * wall_value(!okxp, !okyp, wall[1], wall[3]);
-    f[8] = (okxm && okyp) ? F8[rp + xm] : -F6[n] + tw5 * wall_value(!okxm, !okyp, wall[0], wall[3]);
+    f[1] = okxm ? F1[r0 + xm] : bounce(F3[n], tw1, wall[0]);
+    f[2] = okym ? F2[rm + x] : bounce(F4[n], tw1, wall[2]);
+    f[3] = okxp ? F3[r0 + xp] : bounce(F1[n], tw1, wall[1]);
+    f[4] = okyp ? F4[rp + x] : bounce(F2[n], tw1, wall[3]);
+    f[5] = (okxm && okym) ? F5[rm + xm] : bounce(F7[n], tw5, wall_value(!okxm, !okym, wall[0], wall[2]));
+    f[6] = (okxp && okym) ? F6[rm + xp] : bounce(F8[n], tw5, wall_value(!okxp, !okym, wall[1], wall[2]));
+    f[7] = (okxp && okyp) ? F7[rp + xp] : bounce(F5[n], tw5, wall_value(!okxp, !okyp, wall[1], wall[3]));
+    f[8] = (okxm && okyp) ? F8[rp + xm] : bounce(F6[n], tw5, wall_value(!okxm, !okyp, wall[0], wall[3]));
 }
 
 template <typename T>
@@ -76,7 +93,9 @@ __host__ __device__ inline T sum9(const T f[9])
 }
 
 // One node of the B-TriRT collision in moment space; f holds f(x, t) on entry and
-// f+(x, t) on return. Returns phi(t).
+// f+(x, t) on return. Returns phi(t). The library is built without floating-point
+// contraction: every fused multiply-add below is written out, so a node update rounds the
+// same way in every kernel that inlines it.
 template <typename T, int SRC, bool KPHI>
 __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, T s)
 {
@@ -84,77 +103,82 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     constexpr T sixth = T(1) / T(6);
     constexpr T twelfth = T(1) / T(12);
     constexpr T ninth = T(1) / T(9);
+    constexpr T half = T(0.5), quarter = T(0.25);
 
     // Moments m = T f, rows of Eq. (88).
     const T phi = sum9(f);
-    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const T jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+    const T jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
     const T sd = (f[5] + f[6]) + (f[7] + f[8]);
     const T pxx = (f[1] + f[3]) + sd;
     const T pyy = (f[2] + f[4]) + sd;
     const T pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const T m6 = ((f[5] + f[6]) - (f[7] + f[8])) - third * jy;
-    const T m7 = ((f[5] + f[8]) - (f[6] + f[7])) - third * jx;
-    const T m8 = sd - third * (pxx + pyy);
+    const T m6 = fmadd(-third, jy, (f[5] + f[6]) - (f[7] + f[8]));
+    const T m7 = fmadd(-third, jx, (f[5] + f[8]) - (f[6] + f[7]));
+    const T m8 = fmadd(-third, pxx + pyy, sd);
 
-    // Flux B(phi) and its backward difference over one step (correction G, Eq. (11)).
-    const T Bx = phi * (a.ax + T(0.5) * a.bx * phi);
-    const T By = phi * (a.ay + T(0.5) * a.by * phi);
-    const T dBx = Bx - phi_prev * (a.ax + T(0.5) * a.bx * phi_prev);
-    const T dBy = By - phi_prev * (a.ay + T(0.5) * a.by * phi_prev);
+    // Flux B(phi) = phi (a + b phi / 2) and its backward difference over one step (the
+    // correction G of Eq. (11)).
+    const T hbx = half * a.bx, hby = half * a.by;
+    const T Bx = phi * fmadd(hbx, phi, a.ax);
+    const T By = phi * fmadd(hby, phi, a.ay);
+    const T dBx = fmadd(-phi_prev, fmadd(hbx, phi_prev, a.ax), Bx);
+    const T dBy = fmadd(-phi_prev, fmadd(hby, phi_prev, a.ay), By);
 
-    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)).
+    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)), per node when A depends on phi.
     T K11 = a.K11, K12 = a.K12, K22 = a.K22;
     if constexpr (KPHI) {
-        const T g = T(1) + a.beta * phi * phi;
-        const T m11 = T(3) * a.a11 * g + T(0.5);
-        const T m12 = T(3) * a.a12 * g;
-        const T m22 = T(3) * a.a22 * g + T(0.5);
-        const T rdet = T(1) / (m11 * m22 - m12 * m12);
+        const T g = fmadd(a.beta, phi * phi, T(1));
+        const T m11 = fmadd(T(3) * a.a11, g, half);
+        const T m12 = (T(3) * a.a12) * g;
+        const T m22 = fmadd(T(3) * a.a22, g, half);
+        const T rdet = T(1) / fmadd(m11, m22, -(m12 * m12));
         K11 = m22 * rdet;
         K12 = -m12 * rdet;
         K22 = m11 * rdet;
     }
 
     // Block relaxation (Eq. (99)) towards the equilibrium moments of Eq. (7) with D = phi I:
-    // (phi, B, phi/3, 0, phi/3, 0, 0, -phi/9); source s (Eq. (8)) enters as s (1, 0, 0, 1/3, 0,
-    // 1/3, 0, 0, -1/9); G adds (I - K1/2) dB to j.
+    // (phi, B, phi/3, 0, phi/3, 0, 0, -phi/9); the source s (Eq. (8)) enters as s (1, 0, 0,
+    // 1/3, 0, 1/3, 0, 0, -1/9); G adds (I - K1/2) dB to j.
     const T ex = jx - Bx, ey = jy - By;
-    const T jxp = jx - (K11 * ex + K12 * ey) + dBx - T(0.5) * (K11 * dBx + K12 * dBy);
-    const T jyp = jy - (K12 * ex + K22 * ey) + dBy - T(0.5) * (K12 * dBx + K22 * dBy);
+    const T kex = fmadd(K11, ex, K12 * ey), key = fmadd(K12, ex, K22 * ey);
+    const T kdx = fmadd(K11, dBx, K12 * dBy), kdy = fmadd(K12, dBx, K22 * dBy);
+    const T jxp = fmadd(-half, kdx, (jx - kex) + dBx);
+    const T jyp = fmadd(-half, kdy, (jy - key) + dBy);
     const T phi3 = third * phi;
     const T s3 = third * s;
-    const T pxxp = pxx - a.k2xx * (pxx - phi3) + s3;
-    const T pyyp = pyy - a.k2yy * (pyy - phi3) + s3;
+    const T pxxp = fmadd(-a.k2xx, pxx - phi3, pxx) + s3;
+    const T pyyp = fmadd(-a.k2yy, pyy - phi3, pyy) + s3;
     const T pxyp = (T(1) - a.k2xy) * pxy;
     const T om0 = T(1) - a.k0;
     const T m6p = om0 * m6;
     const T m7p = om0 * m7;
-    const T m8p = m8 - a.k0 * (m8 + ninth * phi) - ninth * s;
+    const T m8p = fmadd(-ninth, s, fmadd(-a.k0, fmadd(ninth, phi, m8), m8));
     const T phip = phi + s;
 
     // f+ = T^-1 m+ (dual basis of the rows of T).
-    f[0] = phip - T(2) * third * (pxxp + pyyp) + m8p;
-    const T c13 = third * pxxp - sixth * pyyp - T(0.5) * m8p;
-    const T d13 = third * jxp - T(0.5) * m7p;
+    const T pp = pxxp + pyyp;
+    f[0] = fmadd(T(-2) * third, pp, phip) + m8p;
+    const T c13 = fmadd(third, pxxp, fmadd(-sixth, pyyp, -half * m8p));
+    const T d13 = fmadd(third, jxp, -half * m7p);
     f[1] = c13 + d13;
     f[3] = c13 - d13;
-    const T c24 = third * pyyp - sixth * pxxp - T(0.5) * m8p;
-    const T d24 = third * jyp - T(0.5) * m6p;
+    const T c24 = fmadd(third, pyyp, fmadd(-sixth, pxxp, -half * m8p));
+    const T d24 = fmadd(third, jyp, -half * m6p);
     f[2] = c24 + d24;
     f[4] = c24 - d24;
-    const T e = twelfth * (pxxp + pyyp) + T(0.25) * m8p;
-    const T h57 = e + T(0.25) * pxyp;
-    const T g57 = twelfth * (jxp + jyp) + T(0.25) * (m6p + m7p);
+    const T e = fmadd(twelfth, pp, quarter * m8p);
+    const T h57 = fmadd(quarter, pxyp, e);
+    const T g57 = fmadd(twelfth, jxp + jyp, quarter * (m6p + m7p));
     f[5] = h57 + g57;
     f[7] = h57 - g57;
-    const T h68 = e - T(0.25) * pxyp;
-    const T g68 = twelfth * (jyp - jxp) + T(0.25) * (m6p - m7p);
+    const T h68 = fmadd(-quarter, pxyp, e);
+    const T g68 = fmadd(twelfth, jyp - jxp, quarter * (m6p - m7p));
     f[6] = h68 + g68;
     f[8] = h68 - g68;
     return phi;
 }
-
 
 // f+(-1) at node (x, y) such that the first pull yields f(0) = f^eq(phi0) (Section 4): a value
 // whose consumer is an interior pull gets f^eq of Eq. (7) (D = phi I) at its destination; a

@@ -92,7 +92,7 @@ def test_bytes_and_workspace():
     for prec, es in ((btrt.F64, 8), (btrt.F32, 4)):
         p = btrt.problem_from_workload(W.c3(), precision=prec)
         info = p.validate()
-        assert info.bytes_per_update == 20 * es
+        assert info.bytes_per_node_launch == 20 * es
         assert info.workspace_bytes == p.workspace_size()
         # Two population buffers of 9 planes dominate the footprint.
         assert info.workspace_bytes >= 2 * 9 * 4096 * 4096 * es

@@ -127,15 +127,30 @@ def test_residual_first_call_compares_to_phi0_and_solve_stops():
         assert s.info().step == 600
 
 
-def test_torch_memory_and_stream_bitwise_identical():
-    # The library's own allocation and a torch workspace on torch's stream give the same bits.
-    w = W.c3().scaled(130, 67, 120)
+@pytest.mark.parametrize("w", [W.c3().scaled(130, 67, 120), W.c2().scaled(1400, 1300, 41)], ids=["small", "nt_stores"])
+def test_torch_memory_and_stream_bitwise_identical(w):
+    # The library's own allocation and a torch workspace on torch's stream give the same bits
+    # (1400 x 1300 FP64 exceeds the 256 MB cache threshold and takes the non-temporal stores).
     a = gpu_run(w)
     b = gpu_run(w, torch_memory=True)
     pa, pb = a.field(), b.field()
     a.close()
     b.close()
     assert np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
+def test_fused_two_step_launch_is_bitwise_identical(w):
+    # Two steps per launch through the on-chip tile must give the bits of two single steps,
+    # for every boundary combination and an odd number of steps.
+    steps = min(w.steps, 151) | 1
+    say(f"[gpu] fused vs single {w.name} {w.nx}x{w.ny} steps={steps}")
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as a, \
+            btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as b:
+        a.set_fusion(1).step(steps)
+        b.set_fusion(2).step(steps)
+        assert np.array_equal(a.populations(), b.populations())
+        assert np.array_equal(a.field(), b.field())
 
 
 def test_step_split_is_bitwise_invariant():
