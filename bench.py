@@ -99,6 +99,50 @@ def timed_run(w, precision, steps, warmup, fusion=2):
     }
 
 
+def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=400):
+    """The 256 uneven FP32 instances: one batched launch per fused step (tuned) against a loop
+    of plain per-instance launches on one stream. Returns MLUPS of both."""
+    import torch
+    from paper_1902_09813_amd import btrt
+    from paper_1902_09813_amd import workloads as W
+
+    ws = W.c4()
+    nodes = sum(w.nx * w.ny for w in ws)
+    probs = [(btrt.problem_from_workload(w, precision=btrt.F32), w.phi0()) for w in ws]
+    stream = torch.cuda.Stream()
+    out = {"instances": len(ws), "nodes": nodes}
+    with btrt.Batch(probs, stream=stream.cuda_stream) as b:
+        best, used = b.tune(tune_steps)
+        b.sync()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        b.step(steps - used)
+        e.record(stream)
+        b.residual()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e)
+        out["batched_mlups"] = round(nodes * (steps - used) / (ms * 1e-3) / 1e6, 1)
+        out["batched_config"] = {"steps_per_launch": best[0], "blocks_per_cu": best[1], "graph_launches": best[2]}
+    with torch.cuda.stream(stream):
+        solvers = [btrt.Solver(btrt.problem_from_workload(w, precision=btrt.F32), ph, torch_memory=True)
+                   for w, (_, ph) in zip(ws, probs)]
+        for s_ in solvers:
+            s_.step(2)
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for s_ in solvers:
+            s_.step(loop_steps)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e)
+        for s_ in solvers:
+            s_.close()
+    out["loop_mlups"] = round(nodes * loop_steps / (ms * 1e-3) / 1e6, 1)
+    out["speedup"] = round(out["batched_mlups"] / out["loop_mlups"], 2)
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
     from oracle import oracle as O
@@ -216,6 +260,9 @@ def main():
         r3 = timed_run(w2, btrt.F64, 2000, 50, args.fusion)
         extra["c2_f64_mlups"] = round(r3["mlups"], 1)
         extra["c2_f64_launch_us"] = round(r3["launch_ms_avg"] * 1e3, 2)
+        print("[bench] side measurement: 256 batched instances vs per-instance loop (f32)", file=sys.stderr,
+              flush=True)
+        extra["batched_c4_f32"] = batched_vs_loop()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -199,6 +199,75 @@ const char* btrt_strerror(int code);
 /* Message of the calling thread's last failed call ("" if none). */
 const char* btrt_last_error(void);
 
+/* ---- many instances in one launch ----------------------------------------------------- */
+/* A batch holds independent problems of different sizes, boundaries and coefficients and
+ * advances all of them together: each sweep launch walks the tiles of every instance, so
+ * one launch (not one per instance) serves the whole batch. Results are bitwise identical to
+ * solving each instance alone with btrt_create/btrt_step. */
+
+typedef struct btrt_batch btrt_batch_t; /* opaque; btrt_batch_create / btrt_batch_destroy */
+
+/* One instance: the arguments of btrt_create, by value. grid.precision must be the same for
+ * every instance of a batch; grid.device, grid.stream and grid.workspace are ignored (the
+ * batch's own apply). phi0 (nx*ny) is copied at create. */
+typedef struct {
+    btrt_grid_t grid;
+    btrt_flux_t B;
+    btrt_diff_t K;
+    btrt_dterm_t D;
+    btrt_source_t R;
+    btrt_bc_t bc;
+    btrt_relax_t relax;
+    const double* phi0;
+} btrt_problem_t;
+
+/* How a batch launches: time steps fused per launch (1 or 2), resident blocks per compute
+ * unit of the persistent grid (0: one block per tile), and launches captured per HIP graph
+ * replay (0: no graph; otherwise even, >= 2). */
+typedef struct {
+    int32_t steps_per_launch;
+    int32_t blocks_per_cu;
+    int32_t graph_launches;
+} btrt_batch_config_t;
+
+/* Creates a batch of n >= 1 instances at t = 0 on `device`, enqueuing on `stream` (NULL: the
+ * library creates one). Device memory is allocated by the library (the sum of the instances'
+ * btrt_workspace_size plus small tables). Errors: any instance failing btrt_validate or
+ * holding a non-finite phi0 -> BTRT_E_INVAL (btrt_last_error names the instance); mixed
+ * precisions -> BTRT_E_INVAL; BTRT_E_DEVICE; BTRT_E_NOMEM. Synchronises. */
+int btrt_batch_create(int32_t n, const btrt_problem_t* problems, int32_t device, void* stream,
+                      btrt_batch_t** out);
+
+/* Enqueues n >= 0 time steps for every instance; returns without waiting. */
+int btrt_batch_step(btrt_batch_t* b, int64_t n);
+
+/* phi(t) of instance i into phi_out[nx_i*ny_i]. Synchronises. */
+int btrt_batch_field(btrt_batch_t* b, int32_t i, double* phi_out);
+
+/* Eq. (64) residual of every instance since its previous check into out[n] (phi0 for the
+ * first). Synchronises. BTRT_E_UNSTABLE if any instance holds NaN/Inf (its entry is NaN). */
+int btrt_batch_residual(btrt_batch_t* b, double* out);
+
+/* Sets / reads the launch configuration (defaults: 2 steps per launch, one block per tile,
+ * no graph). Errors: BTRT_E_INVAL for values outside the ranges above. */
+int btrt_batch_set_config(btrt_batch_t* b, const btrt_batch_config_t* cfg);
+int btrt_batch_get_config(const btrt_batch_t* b, btrt_batch_config_t* cfg);
+
+/* Autotuner: times each candidate configuration on the batch itself by running steps of the
+ * solve (every configuration computes the same bits, so these steps count as ordinary
+ * steps), at most max_steps in total; keeps and reports the fastest. *steps_used = steps
+ * taken. Synchronises. */
+int btrt_batch_tune(btrt_batch_t* b, int64_t max_steps, btrt_batch_config_t* best, int64_t* steps_used);
+
+/* Steps taken so far. */
+int btrt_batch_steps(const btrt_batch_t* b, int64_t* steps);
+
+/* Waits for the batch's stream. */
+int btrt_batch_sync(btrt_batch_t* b);
+
+/* Frees the batch. Synchronises. */
+int btrt_batch_destroy(btrt_batch_t* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,10 @@ K2_VALUE, K2_HBB = 0, 1
 # Every function include/btrt.h declares.
 EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_fusion", "btrt_field",
            "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
-           "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error")
+           "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error",
+           "btrt_batch_create", "btrt_batch_step", "btrt_batch_field", "btrt_batch_residual",
+           "btrt_batch_set_config", "btrt_batch_get_config", "btrt_batch_tune", "btrt_batch_steps",
+           "btrt_batch_sync", "btrt_batch_destroy")
 
 
 class Grid(ctypes.Structure):
@@ -67,6 +70,19 @@ class Info(ctypes.Structure):
                 ("pitch", ctypes.c_int32), ("k1_per_node", ctypes.c_int32), ("K1", ctypes.c_double * 4),
                 ("K2", ctypes.c_double * 4), ("k0", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
                 ("bytes_per_node_launch", ctypes.c_double), ("step", ctypes.c_int64)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("B", Flux), ("K", Diff), ("D", DTerm), ("R", Source), ("bc", BC),
+                ("relax", Relax), ("phi0", ctypes.POINTER(ctypes.c_double))]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("graph_launches", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.steps_per_launch, self.blocks_per_cu, self.graph_launches)
 
 
 class BtrtError(RuntimeError):
@@ -111,6 +127,16 @@ def lib() -> ctypes.CDLL:
             "btrt_sync": ([hp], ctypes.c_int),
             "btrt_get_info": ([hp, P(Info)], ctypes.c_int),
             "btrt_destroy": ([hp], ctypes.c_int),
+            "btrt_batch_create": ([ctypes.c_int32, P(ProblemDesc), ctypes.c_int32, ctypes.c_void_p, P(hp)], ctypes.c_int),
+            "btrt_batch_step": ([hp, ctypes.c_int64], ctypes.c_int),
+            "btrt_batch_field": ([hp, ctypes.c_int32, dp], ctypes.c_int),
+            "btrt_batch_residual": ([hp, dp], ctypes.c_int),
+            "btrt_batch_set_config": ([hp, P(BatchConfig)], ctypes.c_int),
+            "btrt_batch_get_config": ([hp, P(BatchConfig)], ctypes.c_int),
+            "btrt_batch_tune": ([hp, ctypes.c_int64, P(BatchConfig), P(ctypes.c_int64)], ctypes.c_int),
+            "btrt_batch_steps": ([hp, P(ctypes.c_int64)], ctypes.c_int),
+            "btrt_batch_sync": ([hp], ctypes.c_int),
+            "btrt_batch_destroy": ([hp], ctypes.c_int),
             "btrt_strerror": ([ctypes.c_int], ctypes.c_char_p),
             "btrt_last_error": ([], ctypes.c_char_p),
         }
@@ -283,3 +309,75 @@ def problem_from_workload(w, precision: int = F64, device: int = 0, check_interv
     return Problem(w.nx, w.ny, precision=precision, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta,
                    source=w.source, bc_type=w.bc_type, bc_value=w.bc_value, k0=w.k0, k2=w.k2,
                    check_interval=check_interval, device=device)
+
+
+class Batch:
+    """A btrt batch: independent problems advanced together by one launch per (fused) step.
+    ``problems`` is a list of (Problem, phi0) pairs of one precision."""
+
+    def __init__(self, problems, device: int = 0, stream: Optional[int] = None):
+        self.problems = [p for p, _ in problems]
+        self._phi0 = [np.ascontiguousarray(ph, dtype=np.float64).reshape(p.ny, p.nx) for p, ph in problems]
+        arr = (ProblemDesc * len(problems))()
+        for k, (p, _) in enumerate(problems):
+            arr[k] = ProblemDesc(p.grid, p.flux, p.diff, p.dterm, p.source, p.bc, p.relax, _dptr(self._phi0[k]))
+        h = ctypes.c_void_p()
+        _check(lib().btrt_batch_create(len(problems), arr, int(device), stream, ctypes.byref(h)), "btrt_batch_create")
+        self.h = h
+        self.n = len(problems)
+
+    def step(self, n: int) -> "Batch":
+        _check(lib().btrt_batch_step(self.h, int(n)), "btrt_batch_step")
+        return self
+
+    def field(self, i: int) -> np.ndarray:
+        p = self.problems[i]
+        out = np.empty((p.ny, p.nx), dtype=np.float64)
+        _check(lib().btrt_batch_field(self.h, int(i), _dptr(out)), "btrt_batch_field")
+        return out
+
+    def residual(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float64)
+        _check(lib().btrt_batch_residual(self.h, _dptr(out)), "btrt_batch_residual")
+        return out
+
+    def set_config(self, steps_per_launch: int = 2, blocks_per_cu: int = 0, graph_launches: int = 0) -> "Batch":
+        c = BatchConfig(int(steps_per_launch), int(blocks_per_cu), int(graph_launches))
+        _check(lib().btrt_batch_set_config(self.h, ctypes.byref(c)), "btrt_batch_set_config")
+        return self
+
+    def config(self):
+        c = BatchConfig()
+        _check(lib().btrt_batch_get_config(self.h, ctypes.byref(c)), "btrt_batch_get_config")
+        return c.as_tuple()
+
+    def tune(self, max_steps: int):
+        c = BatchConfig()
+        used = ctypes.c_int64()
+        _check(lib().btrt_batch_tune(self.h, int(max_steps), ctypes.byref(c), ctypes.byref(used)), "btrt_batch_tune")
+        return c.as_tuple(), int(used.value)
+
+    def steps(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().btrt_batch_steps(self.h, ctypes.byref(v)), "btrt_batch_steps")
+        return int(v.value)
+
+    def sync(self) -> None:
+        _check(lib().btrt_batch_sync(self.h), "btrt_batch_sync")
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _check(lib().btrt_batch_destroy(self.h), "btrt_batch_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

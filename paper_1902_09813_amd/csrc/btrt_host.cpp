@@ -1,0 +1,414 @@
+// Host-side validation, constants, memory layout and per-instance launch sequence shared by
+// the single-solver and batched C ABI.
+#include "btrt_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace btrth {
+
+using namespace btrtk;
+
+
+namespace {
+thread_local std::string g_last_error;
+inline bool is_finite(double v) { return std::isfinite(v); }
+}  // namespace
+
+const char* last_error() { return g_last_error.c_str(); }
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(BTRT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return BTRT_OK;
+}
+
+int pitch_for(int nx, int precision)
+{
+    const int per = static_cast<int>(kAlign / (precision == BTRT_F64 ? 8 : 4));
+    return (nx + per - 1) / per * per;
+}
+
+Layout layout_for(int nx, int ny, int precision, int src_kind)
+{
+    const size_t es = precision == BTRT_F64 ? 8 : 4;
+    const size_t pitch = static_cast<size_t>(pitch_for(nx, precision));
+    const size_t plane = pitch * static_cast<size_t>(ny);
+    const size_t nn = static_cast<size_t>(nx) * static_cast<size_t>(ny);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.f[0] = take(9 * plane * es);
+    L.f[1] = take(9 * plane * es);
+    L.phi[0] = take(plane * es);
+    L.phi[1] = take(plane * es);
+    // The FP64 phi snapshot of Eq. (64), dense nx*ny.
+    L.snap = take(nn * 8);
+    L.tmp = take(nn * 8);
+    L.partial = take(static_cast<size_t>(kReduceBlocks) * kReducePartials * 8);
+    L.result = take(kReducePartials * 8);
+    L.src = L.src_y = 0;
+    if (src_kind == BTRT_SRC_FIELD) L.src = take(plane * es);
+    if (src_kind == BTRT_SRC_SIN) {
+        L.src = take(static_cast<size_t>(nx) * es);
+        L.src_y = take(static_cast<size_t>(ny) * es);
+    }
+    L.total = off;
+    return L;
+}
+
+bool grid_ok(const btrt_grid_t* g)
+{
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1) return false;
+    if (g->precision != BTRT_F64 && g->precision != BTRT_F32) return false;
+    const int64_t pitch = pitch_for(g->nx, g->precision);
+    // Node and in-plane indices are 32-bit in the kernels.
+    if (static_cast<int64_t>(g->nx) * g->ny > INT32_MAX) return false;
+    if (pitch * (static_cast<int64_t>(g->ny) + 1) > INT32_MAX) return false;
+    return true;
+}
+
+int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
+             const btrt_source_t* R, const btrt_bc_t* bc, const btrt_relax_t* relax, Resolved* res)
+{
+    if (!grid || !B || !K || !D || !bc || !relax) return fail(BTRT_E_INVAL, "NULL argument");
+    if (grid->nx < 1 || grid->ny < 1) return fail(BTRT_E_INVAL, "grid %d x %d: both sides must be >= 1", grid->nx, grid->ny);
+    if (grid->precision != BTRT_F64 && grid->precision != BTRT_F32)
+        return fail(BTRT_E_INVAL, "precision %d is not BTRT_F64 or BTRT_F32", grid->precision);
+    if (!grid_ok(grid)) return fail(BTRT_E_INVAL, "grid %d x %d exceeds 2^31 - 1 nodes", grid->nx, grid->ny);
+    for (int a = 0; a < 2; ++a)
+        if (!is_finite(B->a[a]) || !is_finite(B->b[a])) return fail(BTRT_E_INVAL, "non-finite flux coefficient");
+    if (!is_finite(K->k11) || !is_finite(K->k12) || !is_finite(K->k22) || !is_finite(K->beta))
+        return fail(BTRT_E_INVAL, "non-finite diffusion tensor");
+    if (!(K->k11 > 0.0) || !(K->k22 > 0.0) || !(K->k11 * K->k22 - K->k12 * K->k12 > 0.0))
+        return fail(BTRT_E_INVAL, "diffusion tensor [[%g,%g],[%g,%g]] is not positive definite", K->k11, K->k12,
+                    K->k12, K->k22);
+    if (K->beta < 0.0) return fail(BTRT_E_INVAL, "beta = %g < 0", K->beta);
+    if (D->kind != BTRT_D_PHI_I) return fail(BTRT_E_INVAL, "D kind %d: only D = phi I is supported", D->kind);
+    for (int s = 0; s < 4; ++s) {
+        if (bc->type[s] != BTRT_PERIODIC && bc->type[s] != BTRT_DIRICHLET)
+            return fail(BTRT_E_INVAL, "side %d: boundary type %d", s, bc->type[s]);
+        if (bc->type[s] == BTRT_DIRICHLET && !is_finite(bc->value[s]))
+            return fail(BTRT_E_INVAL, "side %d: non-finite wall value", s);
+    }
+    if ((bc->type[0] == BTRT_PERIODIC) != (bc->type[1] == BTRT_PERIODIC) ||
+        (bc->type[2] == BTRT_PERIODIC) != (bc->type[3] == BTRT_PERIODIC))
+        return fail(BTRT_E_INVAL, "a periodic side must be paired with the opposite side");
+    if (R) {
+        if (R->kind == BTRT_SRC_FIELD) {
+            if (!R->field) return fail(BTRT_E_INVAL, "source field is NULL");
+            const int64_t nn = static_cast<int64_t>(grid->nx) * grid->ny;
+            for (int64_t k = 0; k < nn; ++k)
+                if (!is_finite(R->field[k])) return fail(BTRT_E_INVAL, "non-finite source at node %lld", (long long)k);
+        } else if (R->kind == BTRT_SRC_SIN) {
+            if (!is_finite(R->amp)) return fail(BTRT_E_INVAL, "non-finite source amplitude");
+        } else if (R->kind != BTRT_SRC_NONE) {
+            return fail(BTRT_E_INVAL, "source kind %d", R->kind);
+        }
+    }
+    if (!(relax->k0 > 0.0 && relax->k0 < 2.0)) return fail(BTRT_E_INVAL, "k0 = %g outside (0, 2)", relax->k0);
+    if (relax->check_interval < 1) return fail(BTRT_E_INVAL, "check_interval = %d < 1", relax->check_interval);
+
+    // K1 from Eq. (30): K1 = (A / c_s^2 + I/2)^-1 with A at phi = 0. For an SPD A its
+    // eigenvalues 1/(3 lambda + 1/2) lie in (0, 2).
+    const double m11 = 3.0 * K->k11 + 0.5, m12 = 3.0 * K->k12, m22 = 3.0 * K->k22 + 0.5;
+    const double det = m11 * m22 - m12 * m12;
+    res->K1[0] = m22 / det;
+    res->K1[1] = -m12 / det;
+    res->K1[2] = -m12 / det;
+    res->K1[3] = m11 / det;
+    res->k0 = relax->k0;
+    res->k1_per_node = K->beta != 0.0;
+
+    if (relax->k2_rule == BTRT_K2_HBB) {
+        // Eq. (62) removes the bounce-back slip for K1 = k1 I (Section 3).
+        if (K->k12 != 0.0 || K->k11 != K->k22 || K->beta != 0.0)
+            return fail(BTRT_E_INVAL, "BTRT_K2_HBB needs a constant isotropic A (k11 == k22, k12 == 0, beta == 0)");
+        const double k1 = res->K1[0];
+        const double k2 = 8.0 * (k1 - 2.0) / (3.0 * (k1 - 4.0));
+        for (int q = 0; q < 4; ++q) res->K2[q] = k2;
+    } else if (relax->k2_rule == BTRT_K2_VALUE) {
+        for (int q = 0; q < 4; ++q) {
+            if (!is_finite(relax->k2[q])) return fail(BTRT_E_INVAL, "non-finite k2");
+            res->K2[q] = relax->k2[q];
+        }
+    } else {
+        return fail(BTRT_E_INVAL, "k2 rule %d", relax->k2_rule);
+    }
+    const double kxy = 0.5 * (res->K2[1] + res->K2[2]);
+    if (!(res->K2[0] > 0 && res->K2[0] < 2) || !(res->K2[3] > 0 && res->K2[3] < 2) || !(kxy > 0 && kxy < 2))
+        return fail(BTRT_E_INVAL, "K2 rates (%g, %g, %g) must lie in (0, 2)", res->K2[0], kxy, res->K2[3]);
+    return ok();
+}
+
+void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_t* info)
+{
+    info->nx = g->nx;
+    info->ny = g->ny;
+    info->precision = g->precision;
+    info->pitch = pitch_for(g->nx, g->precision);
+    info->k1_per_node = r.k1_per_node ? 1 : 0;
+    for (int q = 0; q < 4; ++q) {
+        info->K1[q] = r.K1[q];
+        info->K2[q] = r.K2[q];
+    }
+    info->k0 = r.k0;
+    info->workspace_bytes = layout_for(g->nx, g->ny, g->precision, src_kind).total;
+    // 9 population reads + 9 writes + phi(t-1) read + phi(t) write, plus a per-node source.
+    const double es = g->precision == BTRT_F64 ? 8.0 : 4.0;
+    info->bytes_per_node_launch = (20.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * es;
+    info->step = 0;
+}
+
+
+int validate_phi0(const btrt_grid_t* grid, const double* phi0)
+{
+    if (!phi0) return fail(BTRT_E_INVAL, "phi0 is NULL");
+    const size_t nn = static_cast<size_t>(grid->nx) * grid->ny;
+    for (size_t k = 0; k < nn; ++k)
+        if (!is_finite(phi0[k])) return fail(BTRT_E_INVAL, "non-finite phi0 at node %zu", k);
+    return BTRT_OK;
+}
+
+DeviceGuard::DeviceGuard(int device) : device_(device)
+{
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != device_) status_ = hipSetDevice(device_);
+}
+
+DeviceGuard::~DeviceGuard()
+{
+    if (prev_ >= 0 && prev_ != device_) (void)hipSetDevice(prev_);
+}
+
+namespace {
+
+template <typename T>
+void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const btrt_diff_t* K,
+                    const btrt_source_t* R, const Resolved& r)
+{
+    a.plane = I.plane;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.pitch = I.pitch;
+    a.perx = I.perx;
+    a.pery = I.pery;
+    for (int s = 0; s < 4; ++s) a.wall[s] = static_cast<T>(I.wall[s]);
+    a.ax = static_cast<T>(B->a[0]);
+    a.ay = static_cast<T>(B->a[1]);
+    a.bx = static_cast<T>(B->b[0]);
+    a.by = static_cast<T>(B->b[1]);
+    a.a11 = static_cast<T>(K->k11);
+    a.a12 = static_cast<T>(K->k12);
+    a.a22 = static_cast<T>(K->k22);
+    a.beta = static_cast<T>(K->beta);
+    a.K11 = static_cast<T>(r.K1[0]);
+    a.K12 = static_cast<T>(r.K1[1]);
+    a.K22 = static_cast<T>(r.K1[3]);
+    a.k0 = static_cast<T>(r.k0);
+    a.k2xx = static_cast<T>(r.K2[0]);
+    a.k2xy = static_cast<T>(0.5 * (r.K2[1] + r.K2[2]));
+    a.k2yy = static_cast<T>(r.K2[3]);
+    a.src_amp = static_cast<T>(R && R->kind == BTRT_SRC_SIN ? R->amp : 0.0);
+    a.src = I.kind == kSrcNone ? nullptr : reinterpret_cast<const T*>(I.mem + I.L.src);
+    a.src_y = I.kind == kSrcSep ? reinterpret_cast<const T*>(I.mem + I.L.src_y) : nullptr;
+    // Non-temporal stores once the two population buffers exceed the 256 MB Infinity Cache.
+    const double state_bytes = 2.0 * 10.0 * static_cast<double>(I.plane) * sizeof(T);
+    a.nts = state_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
+}
+
+}  // namespace
+
+int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
+                   const btrt_source_t* R, const btrt_bc_t* bc, const Resolved& r, const double* phi0, char* mem,
+                   hipStream_t s)
+{
+    const int src_kind = R ? R->kind : BTRT_SRC_NONE;
+    I.nx = grid->nx;
+    I.ny = grid->ny;
+    I.precision = grid->precision;
+    I.pitch = pitch_for(grid->nx, grid->precision);
+    I.plane = static_cast<int64_t>(I.pitch) * grid->ny;
+    I.kind = src_kind == BTRT_SRC_FIELD ? kSrcField : (src_kind == BTRT_SRC_SIN ? kSrcSep : kSrcNone);
+    I.k1_per_node = r.k1_per_node;
+    I.perx = bc->type[0] == BTRT_PERIODIC;
+    I.pery = bc->type[2] == BTRT_PERIODIC;
+    for (int q = 0; q < 4; ++q) I.wall[q] = bc->type[q] == BTRT_DIRICHLET ? bc->value[q] : 0.0;
+    I.mem = mem;
+    I.L = layout_for(I.nx, I.ny, I.precision, src_kind);
+    I.cur = 0;
+    I.step = 0;
+    fill_info(grid, r, src_kind, &I.info);
+    if (reinterpret_cast<uintptr_t>(mem) % kAlign != 0)
+        return fail(BTRT_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
+
+    const size_t nn = static_cast<size_t>(I.nx) * I.ny;
+    const size_t es = I.precision == BTRT_F64 ? 8 : 4;
+    double* tmp = reinterpret_cast<double*>(mem + I.L.tmp);
+    hipError_t err;
+    // Source of Eq. (8): a per-node field, or separable sin tables at cell centres.
+    if (src_kind == BTRT_SRC_FIELD) {
+        err = hipMemcpyAsync(tmp, R->field, nn * sizeof(double), hipMemcpyHostToDevice, s);
+        if (err != hipSuccess) return hip_fail(err, "source upload");
+        err = I.precision == BTRT_F64
+                  ? launch_convert<double>(tmp, reinterpret_cast<double*>(mem + I.L.src), I.nx, I.ny, I.pitch, s)
+                  : launch_convert<float>(tmp, reinterpret_cast<float*>(mem + I.L.src), I.nx, I.ny, I.pitch, s);
+        if (err != hipSuccess) return hip_fail(err, "source convert");
+        err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+    } else if (src_kind == BTRT_SRC_SIN) {
+        const double pi = 3.14159265358979323846;
+        std::vector<double> sx(I.nx), sy(I.ny);
+        for (int i = 0; i < I.nx; ++i) sx[i] = std::sin(R->kx * pi * (i + 0.5) / I.nx);
+        for (int j = 0; j < I.ny; ++j) sy[j] = std::sin(R->ky * pi * (j + 0.5) / I.ny);
+        std::vector<float> fx, fy;
+        const void* px = sx.data();
+        const void* py = sy.data();
+        if (I.precision == BTRT_F32) {
+            fx.assign(sx.begin(), sx.end());
+            fy.assign(sy.begin(), sy.end());
+            px = fx.data();
+            py = fy.data();
+        }
+        err = hipMemcpyAsync(mem + I.L.src, px, I.nx * es, hipMemcpyHostToDevice, s);
+        if (err == hipSuccess) err = hipMemcpyAsync(mem + I.L.src_y, py, I.ny * es, hipMemcpyHostToDevice, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return hip_fail(err, "source table upload");
+    }
+    if (I.precision == BTRT_F64)
+        fill_constants<double>(I, I.a64, B, K, R, r);
+    else
+        fill_constants<float>(I, I.a32, B, K, R, r);
+
+    err = hipMemcpyAsync(tmp, phi0, nn * sizeof(double), hipMemcpyHostToDevice, s);
+    if (err != hipSuccess) return hip_fail(err, "phi0 upload");
+    if (I.precision == BTRT_F64)
+        err = launch_init<double>(nullptr, reinterpret_cast<double*>(mem + I.L.f[0]),
+                                  reinterpret_cast<double*>(mem + I.L.phi[0]), tmp, I.plane, I.nx, I.ny, I.pitch,
+                                  I.perx, I.pery, I.wall, B->a[0], B->a[1], B->b[0], B->b[1], s);
+    else
+        err = launch_init<float>(nullptr, reinterpret_cast<float*>(mem + I.L.f[0]),
+                                 reinterpret_cast<float*>(mem + I.L.phi[0]), tmp, I.plane, I.nx, I.ny, I.pitch,
+                                 I.perx, I.pery, I.wall, B->a[0], B->a[1], B->b[0], B->b[1], s);
+    if (err != hipSuccess) return hip_fail(err, "init launch");
+    err = hipMemcpyAsync(mem + I.L.snap, tmp, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (err != hipSuccess) return hip_fail(err, "snapshot copy");
+    err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
+    return BTRT_OK;
+}
+
+template <typename T>
+SweepArgs<T> sweep_args(const Instance& I, int parity)
+{
+    SweepArgs<T> a;
+    if constexpr (sizeof(T) == 8)
+        a = I.a64;
+    else
+        a = I.a32;
+    const int nxt = parity ^ 1;
+    a.fin = reinterpret_cast<const T*>(I.mem + I.L.f[parity]);
+    a.fout = reinterpret_cast<T*>(I.mem + I.L.f[nxt]);
+    a.phi_prev = reinterpret_cast<const T*>(I.mem + I.L.phi[parity]);
+    a.phi_out = reinterpret_cast<T*>(I.mem + I.L.phi[nxt]);
+    return a;
+}
+
+template <typename T>
+GatherArgs<T> gather_args(const Instance& I)
+{
+    GatherArgs<T> g{};
+    g.fin = reinterpret_cast<const T*>(I.mem + I.L.f[I.cur]);
+    g.plane = I.plane;
+    g.nx = I.nx;
+    g.ny = I.ny;
+    g.pitch = I.pitch;
+    g.perx = I.perx;
+    g.pery = I.pery;
+    for (int q = 0; q < 4; ++q) g.wall[q] = static_cast<T>(I.wall[q]);
+    g.snap = reinterpret_cast<double*>(I.mem + I.L.snap);
+    g.ref = reinterpret_cast<const double*>(I.mem + I.L.tmp);
+    g.out = reinterpret_cast<double*>(I.mem + I.L.tmp);
+    g.partial = reinterpret_cast<double*>(I.mem + I.L.partial);
+    g.population = -1;
+    return g;
+}
+
+template SweepArgs<double> sweep_args<double>(const Instance&, int);
+template SweepArgs<float> sweep_args<float>(const Instance&, int);
+template GatherArgs<double> gather_args<double>(const Instance&);
+template GatherArgs<float> gather_args<float>(const Instance&);
+
+int instance_launch(Instance& I, int steps, hipStream_t s)
+{
+    hipError_t e;
+    if (I.precision == BTRT_F64)
+        e = launch_sweep<double>(sweep_args<double>(I, I.cur), I.kind, I.k1_per_node, steps, s);
+    else
+        e = launch_sweep<float>(sweep_args<float>(I, I.cur), I.kind, I.k1_per_node, steps, s);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    I.cur ^= 1;
+    I.step += steps;
+    return BTRT_OK;
+}
+
+int instance_reduce_async(Instance& I, int mode, hipStream_t s)
+{
+    double* result = reinterpret_cast<double*>(I.mem + I.L.result);
+    hipError_t e = I.precision == BTRT_F64 ? launch_reduce<double>(gather_args<double>(I), mode, result, s)
+                                           : launch_reduce<float>(gather_args<float>(I), mode, result, s);
+    return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "reduce launch");
+}
+
+int instance_result_async(const Instance& I, double out[kReducePartials], hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(out, I.mem + I.L.result, kReducePartials * sizeof(double), hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "hipMemcpyAsync");
+}
+
+int instance_gather(Instance& I, int population, double* host_out, hipStream_t s)
+{
+    hipError_t e;
+    const size_t nn = static_cast<size_t>(I.nx) * I.ny;
+    if (I.precision == BTRT_F64) {
+        GatherArgs<double> g = gather_args<double>(I);
+        g.population = population;
+        e = launch_gather_field<double>(g, s);
+    } else {
+        GatherArgs<float> g = gather_args<float>(I);
+        g.population = population;
+        e = launch_gather_field<float>(g, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gather launch");
+    e = hipMemcpyAsync(host_out, I.mem + I.L.tmp, nn * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // namespace btrth

@@ -1,0 +1,105 @@
+// Host-side pieces shared by the single-solver and batched C ABI (btrt_api.cpp,
+// btrt_batch.cpp): validation, the constants of Eq. (30) and Eq. (62), the device memory
+// layout of one problem instance, and the per-instance launch sequence.
+#pragma once
+
+#include "btrt.h"
+#include "btrt_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace btrth {
+
+using btrtk::GatherArgs;
+using btrtk::SweepArgs;
+
+// Error reporting: sets the calling thread's last-error message and returns code.
+int fail(int code, const char* fmt, ...);
+int ok();
+int hip_fail(hipError_t e, const char* what);
+const char* last_error();
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Row pitch (elements) of the device planes: rows start on 256-byte boundaries.
+int pitch_for(int nx, int precision);
+
+// Byte offsets of every buffer of one instance inside its memory region.
+struct Layout {
+    size_t f[2], phi[2], snap, tmp, partial, result, src, src_y, total;
+};
+Layout layout_for(int nx, int ny, int precision, int src_kind);
+bool grid_ok(const btrt_grid_t* g);
+
+// Constants derived from a validated problem.
+struct Resolved {
+    double K1[4];  // Eq. (30) at phi = 0
+    double K2[4];  // given, or Eq. (62)
+    double k0;
+    bool k1_per_node;
+};
+
+int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
+             const btrt_source_t* R, const btrt_bc_t* bc, const btrt_relax_t* relax, Resolved* res);
+// Also rejects a NULL or non-finite phi0.
+int validate_phi0(const btrt_grid_t* grid, const double* phi0);
+void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_t* info);
+
+// One problem placed in device memory. State between launches: f+(t-1) in f[cur] and
+// phi(t-1) in phi[cur].
+struct Instance {
+    int nx = 0, ny = 0, pitch = 0, precision = 0;
+    int kind = 0;         // btrtk::SrcKind of the source
+    bool k1_per_node = false;
+    int perx = 1, pery = 1;
+    int64_t plane = 0;
+    double wall[4] = {0, 0, 0, 0};
+    char* mem = nullptr;  // this instance's region; Layout offsets are relative to it
+    Layout L{};
+    int cur = 0;
+    int64_t step = 0;
+    SweepArgs<double> a64{};  // problem constants; buffer pointers are set per launch
+    SweepArgs<float> a32{};
+    btrt_info_t info{};
+};
+
+// Places a validated problem into mem (at least layout_for(...).total bytes, 256-byte
+// aligned): uploads the source and phi0, writes f+(-1) so that the first pull yields
+// f^eq(phi0), phi(-1) := phi0 and the Eq. (64) snapshot := phi0. Synchronises s.
+int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
+                   const btrt_source_t* R, const btrt_bc_t* bc, const Resolved& r, const double* phi0, char* mem,
+                   hipStream_t s);
+
+// Sweep arguments with the buffer pointers for the given parity (0: f[0] -> f[1]).
+template <typename T>
+SweepArgs<T> sweep_args(const Instance& I, int parity);
+template <typename T>
+GatherArgs<T> gather_args(const Instance& I);
+
+// One sweep launch advancing `steps` (1 or 2) time steps; flips the parity.
+int instance_launch(Instance& I, int steps, hipStream_t s);
+// Enqueues the two-pass reduction (residual or error) into I's result slot (no sync).
+int instance_reduce_async(Instance& I, int mode, hipStream_t s);
+// Copies I's result slot to out (async).
+int instance_result_async(const Instance& I, double out[btrtk::kReducePartials], hipStream_t s);
+// phi(t) (population < 0) or f_i(t) into a host array; synchronises.
+int instance_gather(Instance& I, int population, double* host_out, hipStream_t s);
+
+// Runs the enclosed calls with a device current, restoring the caller's afterwards.
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int device);
+    ~DeviceGuard();
+    hipError_t status() const { return status_; }
+
+private:
+    int prev_ = -1;
+    int device_ = 0;
+    hipError_t status_ = hipSuccess;
+};
+
+}  // namespace btrth

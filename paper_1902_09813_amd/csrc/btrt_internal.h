@@ -52,6 +52,15 @@ struct GatherArgs {
     int population;    // population index for the population read, -1 for phi
 };
 
+// One instance of a batched launch: its arguments for both buffer parities and the kernel
+// variant (source kind x per-node K1).
+template <typename T>
+struct BatchEntry {
+    SweepArgs<T> a[2];
+    int variant;  // 2 * source kind + (K1 per node)
+    int pad;
+};
+
 constexpr int kReducePartials = 6; // sum a, sum b, sum c, sum d, max, non-finite count
 constexpr int kReduceBlocks = 1024;
 constexpr int kBlock = 256;
@@ -60,6 +69,15 @@ constexpr int kBlock = 256;
 // steps: 1 (one time step) or 2 (two fused time steps through LDS).
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, int steps, hipStream_t s);
+// All instances of a batch advance `steps` (1 or 2) time steps in one launch of `grid`
+// blocks (0: one block per tile) walking the concatenated tile list.
+template <typename T>
+hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
+                              int flip, int steps, int grid, hipStream_t s);
+// Tile height of the kernel that fuses `steps` steps (tile width is 64).
+int tile_rows(int steps, int precision_bytes);
+constexpr int kTileWidth = 64;
+
 template <typename T>
 hipError_t launch_init(const T* dummy, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx,
                        int ny, int pitch, int perx, int pery, const double wall[4], double ax,

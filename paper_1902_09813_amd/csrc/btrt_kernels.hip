@@ -56,13 +56,10 @@ __device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int 
     return T(0);
 }
 
-// One time step, one thread per node (tile kTileX x kTileY).
+// One time step on tile (tx, ty) of kTileX x kTileY nodes, one node per thread.
 template <typename T, int SRC, bool KPHI>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
+__device__ __forceinline__ void tile1(const SweepArgs<T>& a, int tx, int ty)
 {
-    const int tile = xcd_tile();
-    const int ty = tile / a.tiles_x;
-    const int tx = tile - ty * a.tiles_x;
     const int x = tx * kTileX + static_cast<int>(threadIdx.x % kTileX);
     const int y = ty * kTileY + static_cast<int>(threadIdx.x / kTileX);
     if (x >= a.nx || y >= a.ny) return;
@@ -75,6 +72,14 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
 #pragma unroll
     for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, f[i], a.nts);
     store(a.phi_out + n, phi, a.nts);
+}
+
+template <typename T, int SRC, bool KPHI>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
+{
+    const int tile = xcd_tile();
+    const int ty = tile / a.tiles_x;
+    tile1<T, SRC, KPHI>(a, tile - ty * a.tiles_x, ty);
 }
 
 // Wrap a coordinate of a periodic direction into [0, n) (any distance).
@@ -102,15 +107,11 @@ struct Tile2 {
 };
 
 template <typename T, int SRC, bool KPHI>
-__global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<T> a)
+__device__ __forceinline__ void tile2(const SweepArgs<T>& a, int tx, int ty, T (&lf)[9][Tile2<T>::E],
+                                      T (&lphi)[Tile2<T>::E])
 {
     using G = Tile2<T>;
     constexpr int TX = kTile2X, TY = G::TY, EX = G::EX, E = G::E;
-    __shared__ T lf[9][E];
-    __shared__ T lphi[E];
-    const int tile = xcd_tile();
-    const int ty = tile / a.tiles_x;
-    const int tx = tile - ty * a.tiles_x;
     const int nx = a.nx, ny = a.ny;
     const int x0 = tx * TX - 1, y0 = ty * TY - 1;  // global position of LDS slot (0, 0)
 
@@ -179,6 +180,82 @@ __global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<T> a)
 #pragma unroll
         for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, g[i], a.nts);
         store(a.phi_out + n, phi, a.nts);
+    }
+}
+
+template <typename T, int SRC, bool KPHI>
+__global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<T> a)
+{
+    __shared__ T lf[9][Tile2<T>::E];
+    __shared__ T lphi[Tile2<T>::E];
+    const int tile = xcd_tile();
+    const int ty = tile / a.tiles_x;
+    tile2<T, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, lf, lphi);
+}
+
+// ---- many instances in one launch -------------------------------------------------------
+// The tiles of all instances form one list (instance i owns tiles begin[i] .. begin[i+1]-1).
+// A persistent grid walks the list; each tile reads its instance's arguments (uniform per
+// block, so they land in scalar registers) and runs the same tile body as a single solve.
+// Instance i's buffers swap every launch: it uses a[par[i] ^ flip].
+
+// Instance index owning tile t: the last i with begin[i] <= t.
+__device__ __forceinline__ int owner(const int* __restrict__ begin, int ninst, int t)
+{
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __restrict__ ent,
+                                                        const int* __restrict__ begin, const int* __restrict__ par,
+                                                        int ninst, int total, int flip)
+{
+    const int g = static_cast<int>(gridDim.x);
+    for (int t = xcd_tile(); t < total; t += g) {
+        const int i = owner(begin, ninst, t);
+        const SweepArgs<T> a = ent[i].a[par[i] ^ flip];
+        const int local = t - begin[i];
+        const int tiles_x = (a.nx + kTileX - 1) / kTileX;
+        const int ty = local / tiles_x, tx = local - ty * tiles_x;
+        switch (ent[i].variant) {
+            case 0: tile1<T, kSrcNone, false>(a, tx, ty); break;
+            case 1: tile1<T, kSrcNone, true>(a, tx, ty); break;
+            case 2: tile1<T, kSrcField, false>(a, tx, ty); break;
+            case 3: tile1<T, kSrcField, true>(a, tx, ty); break;
+            case 4: tile1<T, kSrcSep, false>(a, tx, ty); break;
+            default: tile1<T, kSrcSep, true>(a, tx, ty); break;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __restrict__ ent,
+                                                         const int* __restrict__ begin, const int* __restrict__ par,
+                                                         int ninst, int total, int flip)
+{
+    __shared__ T lf[9][Tile2<T>::E];
+    __shared__ T lphi[Tile2<T>::E];
+    const int g = static_cast<int>(gridDim.x);
+    for (int t = xcd_tile(); t < total; t += g) {
+        const int i = owner(begin, ninst, t);
+        const SweepArgs<T> a = ent[i].a[par[i] ^ flip];
+        const int local = t - begin[i];
+        const int tiles_x = (a.nx + kTile2X - 1) / kTile2X;
+        const int ty = local / tiles_x, tx = local - ty * tiles_x;
+        switch (ent[i].variant) {
+            case 0: tile2<T, kSrcNone, false>(a, tx, ty, lf, lphi); break;
+            case 1: tile2<T, kSrcNone, true>(a, tx, ty, lf, lphi); break;
+            case 2: tile2<T, kSrcField, false>(a, tx, ty, lf, lphi); break;
+            case 3: tile2<T, kSrcField, true>(a, tx, ty, lf, lphi); break;
+            case 4: tile2<T, kSrcSep, false>(a, tx, ty, lf, lphi); break;
+            default: tile2<T, kSrcSep, true>(a, tx, ty, lf, lphi); break;
+        }
+        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
@@ -348,6 +425,25 @@ hipError_t launch_sweep(const SweepArgs<T>& a_in, int src_kind, bool k1_per_node
 }
 
 template <typename T>
+hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
+                              int flip, int steps, int grid, hipStream_t s)
+{
+    if (total_tiles <= 0 || ninst <= 0) return hipSuccess;
+    const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid, total_tiles) : total_tiles);
+    if (steps == 2)
+        hipLaunchKernelGGL((batch2_kernel<T>), dim3(g), dim3(kBlock2), 0, s, ent, begin, par, ninst, total_tiles, flip);
+    else
+        hipLaunchKernelGGL((batch1_kernel<T>), dim3(g), dim3(kBlock), 0, s, ent, begin, par, ninst, total_tiles, flip);
+    return hipGetLastError();
+}
+
+int tile_rows(int steps, int precision_bytes)
+{
+    if (steps == 2) return precision_bytes == 8 ? Tile2<double>::TY : Tile2<float>::TY;
+    return kTileY;
+}
+
+template <typename T>
 hipError_t launch_init(const T*, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx, int ny,
                        int pitch, int perx, int pery, const double wall[4], double ax, double ay,
                        double bx, double by, hipStream_t s)
@@ -395,7 +491,9 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
                                        const double[4], double, double, double, double, hipStream_t);        \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, hipStream_t);                          \
     template hipError_t launch_reduce<T>(const GatherArgs<T>&, int, double*, hipStream_t);                  \
-    template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);
+    template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);                     \
+    template hipError_t launch_batch_sweep<T>(const BatchEntry<T>*, const int*, const int*, int, int, int, int, int, \
+                                              hipStream_t);
 
 BTRT_INSTANTIATE(double)
 BTRT_INSTANTIATE(float)

@@ -16,6 +16,12 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           S = 0, phi0 = sum of 16 Gaussians (seed 3; amplitude U[0, 1], sigma U[8, 64], centre
           U[0, 4096)^2, minimum-image distance), k0 = k2 = 1, 5000 steps.
 
+* ``c4``  256 independent instances (seed 4): side N = round(exp(U[ln 32, ln 512])), k11, k22 ~
+          U[0.005, 0.05], k12 ~ U[-0.5, 0.5] sqrt(k11 k22), u ~ U[-0.05, 0.05]^2; a seeded coin
+          picks periodic or Dirichlet sides. Dirichlet: per-side phi_w ~ U[0, 1] and
+          S = r0 sin(pi x/N) sin(pi y/N); periodic: S = r0 sin(2 pi x/N) sin(2 pi y/N) (zero
+          mean); r0 ~ U[0, 1e-4]; phi0 ~ U[0, 1); k0 = k2 = 1; FP32 storage, 2000 steps.
+
 ``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
 sizes; ragged sizes exercise partial tiles).
 """
@@ -105,3 +111,25 @@ def initial_field(w: Workload) -> np.ndarray:
             out += a * np.exp(-(dx * dx + dy * dy) / (2.0 * s * s))
         return out
     raise ValueError(w.phi0_kind)
+
+
+def c4(count: int = 256, seed: int = 4, steps: int = 2000, side_range=(32, 512)) -> list:
+    """The batched workload: a list of independent square instances (see the module notes)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    lo, hi = np.log(side_range[0]), np.log(side_range[1])
+    for k in range(count):
+        n = int(round(np.exp(rng.uniform(lo, hi))))
+        k11, k22 = rng.uniform(0.005, 0.05, 2)
+        k12 = rng.uniform(-0.5, 0.5) * np.sqrt(k11 * k22)
+        u = rng.uniform(-0.05, 0.05, 2)
+        r0 = rng.uniform(0.0, 1e-4)
+        if rng.random() < 0.5:
+            bc_type, bc_value, src = (PERIODIC,) * 4, (0.0,) * 4, ("sin", r0, 2, 2)
+        else:
+            bc_type, bc_value, src = (DIRICHLET,) * 4, tuple(rng.uniform(0.0, 1.0, 4)), ("sin", r0, 1, 1)
+        out.append(Workload(f"c4_{k:03d}_{n}", n, n, steps, flux_a=(float(u[0]), float(u[1])),
+                            A0=(float(k11), float(k12), float(k22)), source=src, bc_type=bc_type,
+                            bc_value=tuple(float(v) for v in bc_value), k0=1.0, k2=1.0,
+                            seed=int(rng.integers(1 << 31)), phi0_kind="uniform"))
+    return out
