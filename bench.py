@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -143,6 +145,67 @@ def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=400):
     return out
 
 
+def served(duration_s=20.0, calib_requests=12, seed=5):
+    """Served solves: Poisson arrivals of FP32 requests (side 64..2048, residual <= 1e-8 or
+    50000 steps) into the continuous-batching server. The arrival rate is 0.8 x the rate the
+    server sustains on a backlog (calibration run). Time to solution is measured from each
+    request's scheduled arrival to its completion, on the server clock."""
+    import torch
+    from paper_1902_09813_amd import btrt
+    from paper_1902_09813_amd import workloads as W
+
+    stream = torch.cuda.Stream()
+    opts = dict(precision=btrt.F32, memory_bytes=48 << 30, max_active=128, check_interval=1000,
+                launch=(2, 0, 0), stream=stream.cuda_stream)
+    # Calibration: a backlog of requests submitted at once.
+    calib = W.c5(calib_requests, rate=1.0, seed=seed + 7)
+    with btrt.Server(**opts) as srv:
+        ids = [srv.submit(btrt.problem_from_workload(w, precision=btrt.F32), w.phi0(), tol, ms)
+               for _, w, tol, ms in calib]
+        t0 = srv.clock()
+        while any(srv.info(i)["status"] < btrt.REQ_DONE for i in ids):
+            srv.pump()
+        sustain = calib_requests / (srv.clock() - t0)
+    rate = 0.8 * sustain
+    n_req = max(4, int(rate * duration_s))
+    reqs = W.c5(n_req, rate=rate, seed=seed)
+    lat, done_ids = [], []
+    with btrt.Server(**opts) as srv:
+        start = srv.clock()
+        pending = list(reqs)
+        sched = {}
+        while pending or any(srv.info(i)["status"] < btrt.REQ_DONE for i in sched):
+            now = srv.clock() - start
+            while pending and pending[0][0] <= now:
+                t_arr, w, tol, ms = pending.pop(0)
+                rid = srv.submit(btrt.problem_from_workload(w, precision=btrt.F32), w.phi0(), tol, ms)
+                sched[rid] = start + t_arr
+            active, queued = srv.pump()
+            if active == 0 and queued == 0 and pending:
+                time.sleep(max(0.0, min(0.05, pending[0][0] - (srv.clock() - start))))
+        end = srv.clock()
+        st = srv.stats()
+        steps = []
+        for rid, t_arr in sched.items():
+            info = srv.info(rid)
+            lat.append(info["t_done"] - t_arr)
+            steps.append(info["steps"])
+    lat = np.sort(np.array(lat))
+    return {
+        "requests": n_req,
+        "rate_per_s": round(rate, 3),
+        "sustained_rate_per_s": round(sustain, 3),
+        "p50_s": round(float(np.percentile(lat, 50)), 3),
+        "p99_s": round(float(np.percentile(lat, 99)), 3),
+        "mean_steps": round(float(np.mean(steps)), 1),
+        "aggregate_mlups": round(st["node_updates"] / (end - start) / 1e6, 1),
+        "wall_s": round(end - start, 2),
+        "completed": st["completed"],
+        "failed": st["failed"],
+        "memory_high_water_gb": round(st["memory_high_water"] / 1e9, 2),
+    }
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
     from oracle import oracle as O
@@ -202,6 +265,8 @@ def main():
     ap.add_argument("--fusion", type=int, choices=[1, 2], default=2, help="time steps per sweep launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served measurement")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
 
@@ -263,6 +328,9 @@ def main():
         print("[bench] side measurement: 256 batched instances vs per-instance loop (f32)", file=sys.stderr,
               flush=True)
         extra["batched_c4_f32"] = batched_vs_loop()
+    if not args.no_serve:
+        print("[bench] side measurement: served requests (continuous batching)", file=sys.stderr, flush=True)
+        extra["served_c5_f32"] = served(args.serve_seconds)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -268,6 +268,78 @@ int btrt_batch_sync(btrt_batch_t* b);
 /* Frees the batch. Synchronises. */
 int btrt_batch_destroy(btrt_batch_t* b);
 
+/* ---- solve server (continuous batching) ------------------------------------------------ */
+/* Requests (one problem each, solved to a residual tolerance or a step cap) arrive at any
+ * time. Each btrt_server_pump call is one scheduling round: it admits queued requests in
+ * arrival order while their device footprint fits in the server's memory and a slot is free
+ * (a request that does not fit lets later, smaller ones pass), advances every resident request
+ * by check_interval steps with batched launches (their work shares each launch), evaluates the
+ * Eq. (64) residual of each, and retires those at tolerance, at their step cap, or unstable,
+ * keeping their phi on the host until collected. A request takes whole rounds, so its result
+ * is bitwise the same whether it runs alone or among others. Not thread safe. */
+
+typedef struct btrt_server btrt_server_t; /* opaque; btrt_server_create / btrt_server_destroy */
+
+#define BTRT_REQ_QUEUED 0
+#define BTRT_REQ_RUNNING 1
+#define BTRT_REQ_DONE 2   /* converged (residual <= tol) or reached its step cap */
+#define BTRT_REQ_FAILED 3 /* NaN/Inf seen (error = BTRT_E_UNSTABLE) */
+
+typedef struct {
+    int32_t precision;          /* BTRT_F64 or BTRT_F32, for every request */
+    int32_t device;
+    void* stream;               /* hipStream_t; NULL: the server creates one */
+    size_t memory_bytes;        /* device memory reserved for resident requests */
+    int32_t max_active;         /* resident requests at most (>= 1) */
+    int32_t check_interval;     /* steps per round; the residual is checked after each round */
+    btrt_batch_config_t launch; /* launch configuration of the batched sweeps */
+} btrt_server_opts_t;
+
+typedef struct {
+    int32_t status;  /* BTRT_REQ_* */
+    int32_t error;   /* BTRT_OK, or the failure code */
+    int32_t nx, ny;
+    int64_t steps;   /* steps taken */
+    double residual; /* last Eq. (64) residual (NaN before the first check) */
+    double t_submit, t_admit, t_done; /* seconds on the server clock (-1: not yet) */
+} btrt_request_info_t;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int32_t active, queued;
+    int64_t node_updates;   /* node updates executed for all requests */
+    double busy_seconds;    /* wall time spent inside btrt_server_pump */
+    size_t memory_in_use, memory_high_water;
+} btrt_server_stats_t;
+
+/* Creates a server and reserves opts->memory_bytes of device memory. Errors: BTRT_E_INVAL
+ * (bad options), BTRT_E_DEVICE, BTRT_E_NOMEM. */
+int btrt_server_create(const btrt_server_opts_t* opts, btrt_server_t** out);
+
+/* Queues one request: solve p until the residual is <= tol or max_steps steps (rounded up to
+ * whole rounds). p's host arrays are copied. *id receives the request id. Errors: those of
+ * btrt_validate, non-finite phi0, a precision other than the server's -> BTRT_E_INVAL; a
+ * footprint larger than the server's memory -> BTRT_E_NOMEM. */
+int btrt_server_submit(btrt_server_t* s, const btrt_problem_t* p, double tol, int64_t max_steps, int64_t* id);
+
+/* One scheduling round (see above). Reports resident and queued counts. Synchronises. */
+int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued);
+
+/* State of request id. Errors: BTRT_E_INVAL for an unknown or collected id. */
+int btrt_server_info(const btrt_server_t* s, int64_t id, btrt_request_info_t* info);
+
+/* phi of a DONE request into phi_out[nx*ny]; releases the request. Errors: BTRT_E_INVAL for an
+ * unknown id or a request that is not DONE. */
+int btrt_server_result(btrt_server_t* s, int64_t id, double* phi_out);
+
+int btrt_server_stats(const btrt_server_t* s, btrt_server_stats_t* stats);
+
+/* Seconds since the server was created (the clock of btrt_request_info_t). */
+double btrt_server_clock(const btrt_server_t* s);
+
+/* Frees the server, its device memory and every request. Synchronises. */
+int btrt_server_destroy(btrt_server_t* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,9 @@ EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "
            "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error",
            "btrt_batch_create", "btrt_batch_step", "btrt_batch_field", "btrt_batch_residual",
            "btrt_batch_set_config", "btrt_batch_get_config", "btrt_batch_tune", "btrt_batch_steps",
-           "btrt_batch_sync", "btrt_batch_destroy")
+           "btrt_batch_sync", "btrt_batch_destroy",
+           "btrt_server_create", "btrt_server_submit", "btrt_server_pump", "btrt_server_info",
+           "btrt_server_result", "btrt_server_stats", "btrt_server_clock", "btrt_server_destroy")
 
 
 class Grid(ctypes.Structure):
@@ -85,6 +87,32 @@ class BatchConfig(ctypes.Structure):
         return (self.steps_per_launch, self.blocks_per_cu, self.graph_launches)
 
 
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("memory_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("check_interval", ctypes.c_int32), ("launch", BatchConfig)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("error", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("steps", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("node_updates", ctypes.c_int64), ("busy_seconds", ctypes.c_double),
+                ("memory_in_use", ctypes.c_size_t), ("memory_high_water", ctypes.c_size_t)]
+
+
+def _struct_dict(st):
+    return {name: getattr(st, name) for name, _ in st._fields_}
+
+
 class BtrtError(RuntimeError):
     def __init__(self, code: int, where: str, msg: str):
         self.code = code
@@ -137,6 +165,14 @@ def lib() -> ctypes.CDLL:
             "btrt_batch_steps": ([hp, P(ctypes.c_int64)], ctypes.c_int),
             "btrt_batch_sync": ([hp], ctypes.c_int),
             "btrt_batch_destroy": ([hp], ctypes.c_int),
+            "btrt_server_create": ([P(ServerOpts), P(hp)], ctypes.c_int),
+            "btrt_server_submit": ([hp, P(ProblemDesc), ctypes.c_double, ctypes.c_int64, P(ctypes.c_int64)], ctypes.c_int),
+            "btrt_server_pump": ([hp, P(ctypes.c_int32), P(ctypes.c_int32)], ctypes.c_int),
+            "btrt_server_info": ([hp, ctypes.c_int64, P(RequestInfo)], ctypes.c_int),
+            "btrt_server_result": ([hp, ctypes.c_int64, dp], ctypes.c_int),
+            "btrt_server_stats": ([hp, P(ServerStats)], ctypes.c_int),
+            "btrt_server_clock": ([hp], ctypes.c_double),
+            "btrt_server_destroy": ([hp], ctypes.c_int),
             "btrt_strerror": ([ctypes.c_int], ctypes.c_char_p),
             "btrt_last_error": ([], ctypes.c_char_p),
         }
@@ -368,6 +404,70 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "h", None):
             _check(lib().btrt_batch_destroy(self.h), "btrt_batch_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A btrt solve server (continuous batching). Requests are (Problem, phi0, tol, max_steps);
+    ``pump`` runs one scheduling round."""
+
+    def __init__(self, precision: int = F32, memory_bytes: int = 8 << 30, max_active: int = 64,
+                 check_interval: int = 1000, launch=(2, 0, 0), device: int = 0, stream: Optional[int] = None):
+        o = ServerOpts(int(precision), int(device), stream, int(memory_bytes), int(max_active), int(check_interval),
+                       BatchConfig(*[int(v) for v in launch]))
+        h = ctypes.c_void_p()
+        _check(lib().btrt_server_create(ctypes.byref(o), ctypes.byref(h)), "btrt_server_create")
+        self.h = h
+        self._shape = {}
+
+    def submit(self, problem: Problem, phi0: np.ndarray, tol: float, max_steps: int) -> int:
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(problem.ny, problem.nx)
+        d = ProblemDesc(problem.grid, problem.flux, problem.diff, problem.dterm, problem.source, problem.bc,
+                        problem.relax, _dptr(phi0))
+        rid = ctypes.c_int64()
+        _check(lib().btrt_server_submit(self.h, ctypes.byref(d), float(tol), int(max_steps), ctypes.byref(rid)),
+               "btrt_server_submit")
+        self._shape[rid.value] = (problem.ny, problem.nx)
+        return int(rid.value)
+
+    def pump(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().btrt_server_pump(self.h, ctypes.byref(a), ctypes.byref(q)), "btrt_server_pump")
+        return int(a.value), int(q.value)
+
+    def info(self, rid: int) -> dict:
+        st = RequestInfo()
+        _check(lib().btrt_server_info(self.h, int(rid), ctypes.byref(st)), "btrt_server_info")
+        return _struct_dict(st)
+
+    def result(self, rid: int) -> np.ndarray:
+        out = np.empty(self._shape[rid], dtype=np.float64)
+        _check(lib().btrt_server_result(self.h, int(rid), _dptr(out)), "btrt_server_result")
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().btrt_server_stats(self.h, ctypes.byref(st)), "btrt_server_stats")
+        return _struct_dict(st)
+
+    def clock(self) -> float:
+        return float(lib().btrt_server_clock(self.h))
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _check(lib().btrt_server_destroy(self.h), "btrt_server_destroy")
             self.h = None
 
     def __enter__(self):

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbtrt.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("btrt_host.cpp", "btrt_api.cpp", "btrt_batch.cpp", "btrt_kernels.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("btrt_host.cpp", "btrt_group.cpp", "btrt_api.cpp", "btrt_batch.cpp", "btrt_server.cpp", "btrt_kernels.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -10,6 +10,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace btrth {
 
@@ -88,6 +89,41 @@ int instance_reduce_async(Instance& I, int mode, hipStream_t s);
 int instance_result_async(const Instance& I, double out[btrtk::kReducePartials], hipStream_t s);
 // phi(t) (population < 0) or f_i(t) into a host array; synchronises.
 int instance_gather(Instance& I, int population, double* host_out, hipStream_t s);
+
+// A set of resident instances advanced together by batched launches (used by the batch and
+// the server). Device tables are sized for `capacity` instances; membership may change
+// between calls (group_upload rebuilds the tables).
+struct Group {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = BTRT_F64;
+    int ncu = 256;
+    int capacity = 0;
+    std::vector<Instance*> inst;
+    char* tables = nullptr;  // device: entries, tile offsets (1- and 2-step tiles), parities
+    void* d_ent = nullptr;
+    int* d_begin[3] = {nullptr, nullptr, nullptr};
+    int* d_par = nullptr;
+    int total[3] = {0, 0, 0};
+    int flip = 0;  // launches since group_upload, mod 2
+    btrt_batch_config_t cfg{2, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    btrt_batch_config_t gcfg{0, 0, 0};
+    double* h_res = nullptr;  // pinned, capacity * kReducePartials
+};
+
+int group_init(Group& g, int device, hipStream_t s, int precision, int capacity);
+// Rebuilds the device tables from g.inst (synchronous); drops the captured graph.
+int group_upload(Group& g);
+// Enqueues n time steps of every member.
+int group_enqueue(Group& g, int64_t n);
+// Eq. (64) residual of every member into out[size]; *bad = members with NaN/Inf (out NaN).
+int group_residuals(Group& g, double* out, int* bad);
+// Times candidate configurations on the members' own steps; keeps the fastest.
+int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* used);
+bool config_ok(const btrt_batch_config_t* c);
+void group_free(Group& g);
 
 // Runs the enclosed calls with a device current, restoring the caller's afterwards.
 class DeviceGuard {

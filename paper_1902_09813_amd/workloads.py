@@ -22,6 +22,11 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           S = r0 sin(pi x/N) sin(pi y/N); periodic: S = r0 sin(2 pi x/N) sin(2 pi y/N) (zero
           mean); r0 ~ U[0, 1e-4]; phi0 ~ U[0, 1); k0 = k2 = 1; FP32 storage, 2000 steps.
 
+* ``c5``  served requests (seed 5): Poisson arrival times at a given rate; side N log-uniform in
+          [64, 2048]; coefficients, boundaries, sources and phi0 drawn as for ``c4``; half of
+          the requests (seeded coin) use A(phi) = A0 (1 + phi^2); each runs until the Eq. (64)
+          residual is <= 1e-8 or 50000 steps; FP32 storage.
+
 ``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
 sizes; ragged sizes exercise partial tiles).
 """
@@ -132,4 +137,20 @@ def c4(count: int = 256, seed: int = 4, steps: int = 2000, side_range=(32, 512))
                             A0=(float(k11), float(k12), float(k22)), source=src, bc_type=bc_type,
                             bc_value=tuple(float(v) for v in bc_value), k0=1.0, k2=1.0,
                             seed=int(rng.integers(1 << 31)), phi0_kind="uniform"))
+    return out
+
+
+def c5(count: int, rate: float, seed: int = 5, side_range=(64, 2048), tol: float = 1e-8,
+       max_steps: int = 50000) -> list:
+    """Served requests: a list of (arrival time in seconds, Workload, tol, max_steps)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    base = c4(count=count, seed=seed + 1000, steps=max_steps, side_range=side_range)
+    out = []
+    for k, w in enumerate(base):
+        t += rng.exponential(1.0 / rate)
+        if rng.random() < 0.5:
+            w.beta = 1.0
+        w.name = f"c5_{k:04d}_{w.nx}"
+        out.append((t, w, tol, max_steps))
     return out
