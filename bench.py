@@ -261,7 +261,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--precision", choices=["f64", "f32", "f16dev", "bf16dev"], default="f64")
     ap.add_argument("--fusion", type=int, choices=[1, 2], default=2, help="time steps per sweep launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
@@ -288,7 +288,8 @@ def main():
     from paper_1902_09813_amd import btrt
     from paper_1902_09813_amd import workloads as W
 
-    prec = btrt.F64 if args.precision == "f64" else btrt.F32
+    precisions = {"f64": btrt.F64, "f32": btrt.F32, "f16dev": btrt.F16DEV, "bf16dev": btrt.BF16DEV}
+    prec = precisions[args.precision]
     w = W.c3()
     print(f"[bench] {w.name} {args.precision}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
           flush=True)
@@ -309,13 +310,14 @@ def main():
     }
     extra = {}
     if not args.no_extra:
-        other = btrt.F32 if prec == btrt.F64 else btrt.F64
-        name = "f32" if other == btrt.F32 else "f64"
-        print(f"[bench] side measurement: {w.name} {name}", file=sys.stderr, flush=True)
-        r2 = timed_run(w, other, min(args.steps, 2000), 50, args.fusion)
-        extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
-        extra[f"c3_{name}_hbm_frac"] = round(r2["bytes_per_node_launch"] * r2["nodes"] / (r2["launch_ms_avg"] * 1e-3)
-                                             / 1e9 / HBM_PEAK_GBS, 4)
+        for name, other in precisions.items():
+            if other == prec:
+                continue
+            print(f"[bench] side measurement: {w.name} {name}", file=sys.stderr, flush=True)
+            r2 = timed_run(w, other, min(args.steps, 2000), 50, args.fusion)
+            extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
+            extra[f"c3_{name}_hbm_frac"] = round(
+                r2["bytes_per_node_launch"] * r2["nodes"] / (r2["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         r1 = timed_run(w, prec, min(args.steps, 1000), 20, 1)
         extra[f"c3_{args.precision}_one_step_per_launch_mlups"] = round(r1["mlups"], 1)
         extra[f"c3_{args.precision}_one_step_per_launch_hbm_frac"] = round(
@@ -347,11 +349,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": "f64" if prec == btrt.F64 else "f32",
         "data": "synthetic (seeded 16-Gaussian initial field, lattice units)",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "boundary": "periodic",
                    "flux": "B = 0.025 phi^2 (1, 1)", "diffusion": "A = diag(0.01, 0.005)(1 + phi^2)",
-                   "k0": 1.0, "k2": 1.0, "residual_check_interval": CHECK_INTERVAL, "parallelism": "single GPU"},
+                   "k0": 1.0, "k2": 1.0, "residual_check_interval": CHECK_INTERVAL, "parallelism": "single GPU",
+                   "population_storage": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

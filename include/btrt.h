@@ -49,8 +49,12 @@ extern "C" {
 #define BTRT_E_STATE 5    /* NULL handle */
 
 /* ---- enumerations ------------------------------------------------------------------ */
-#define BTRT_F64 0 /* populations stored and collided in FP64 */
-#define BTRT_F32 1 /* populations stored and collided in FP32 (reductions stay FP64) */
+#define BTRT_F64 0     /* populations stored and collided in FP64 */
+#define BTRT_F32 1     /* populations stored and collided in FP32 (reductions stay FP64) */
+#define BTRT_F16DEV 2  /* populations stored as FP16 scaled deviations from equilibrium,
+                          h = q(s (f+ - f_eq(phi))) with phi in FP32 and a power-of-two s set
+                          at create from max|phi0|; FP32 collision; single handles only */
+#define BTRT_BF16DEV 3 /* the same with BF16 deviations */
 
 #define BTRT_PERIODIC 0
 #define BTRT_DIRICHLET 1 /* half-way bounce-back, Eqs. (54)-(56) */
@@ -69,7 +73,7 @@ typedef struct btrt btrt_t; /* opaque; created by btrt_create, released by btrt_
 
 typedef struct {
     int32_t nx, ny;         /* nodes along x and y, each >= 1; nx*ny <= 2^31 - 1 */
-    int32_t precision;      /* BTRT_F64 or BTRT_F32 */
+    int32_t precision;      /* BTRT_F64, BTRT_F32, BTRT_F16DEV or BTRT_BF16DEV */
     int32_t device;         /* HIP device ordinal */
     void* stream;           /* hipStream_t to enqueue on; NULL: the library creates one */
     void* workspace;        /* device memory owned by the caller, >= btrt_workspace_size();

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libbtrt.so")
 
 # Constants of include/btrt.h.
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, 1, 2, 3, 4, 5
-F64, F32 = 0, 1
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, DIRICHLET = 0, 1
 SRC_NONE, SRC_FIELD, SRC_SIN = 0, 1, 2
 D_PHI_I = 0

@@ -43,15 +43,27 @@ int ok()
     return BTRT_OK;
 }
 
+size_t pop_bytes(int precision)
+{
+    return precision == BTRT_F64 ? 8 : (precision == BTRT_F32 ? 4 : 2);
+}
+
+int format_of(int precision)
+{
+    return precision == BTRT_F16DEV ? kFmtF16Dev : (precision == BTRT_BF16DEV ? kFmtBF16Dev : kFmtPlain);
+}
+
 int pitch_for(int nx, int precision)
 {
-    const int per = static_cast<int>(kAlign / (precision == BTRT_F64 ? 8 : 4));
+    // 16-bit deviation formats share the pitch of their FP32 phi plane: 128 elements.
+    const int per = static_cast<int>(kAlign / (precision == BTRT_F64 ? 8 : (precision == BTRT_F32 ? 4 : 2)));
     return (nx + per - 1) / per * per;
 }
 
 Layout layout_for(int nx, int ny, int precision, int src_kind)
 {
-    const size_t es = precision == BTRT_F64 ? 8 : 4;
+    const size_t es = pop_bytes(precision);     // one population value
+    const size_t ps = precision == BTRT_F64 ? 8 : 4;  // phi and source values
     const size_t pitch = static_cast<size_t>(pitch_for(nx, precision));
     const size_t plane = pitch * static_cast<size_t>(ny);
     const size_t nn = static_cast<size_t>(nx) * static_cast<size_t>(ny);
@@ -64,18 +76,18 @@ Layout layout_for(int nx, int ny, int precision, int src_kind)
     };
     L.f[0] = take(9 * plane * es);
     L.f[1] = take(9 * plane * es);
-    L.phi[0] = take(plane * es);
-    L.phi[1] = take(plane * es);
+    L.phi[0] = take(plane * ps);
+    L.phi[1] = take(plane * ps);
     // The FP64 phi snapshot of Eq. (64), dense nx*ny.
     L.snap = take(nn * 8);
     L.tmp = take(nn * 8);
     L.partial = take(static_cast<size_t>(kReduceBlocks) * kReducePartials * 8);
     L.result = take(kReducePartials * 8);
     L.src = L.src_y = 0;
-    if (src_kind == BTRT_SRC_FIELD) L.src = take(plane * es);
+    if (src_kind == BTRT_SRC_FIELD) L.src = take(plane * ps);
     if (src_kind == BTRT_SRC_SIN) {
-        L.src = take(static_cast<size_t>(nx) * es);
-        L.src_y = take(static_cast<size_t>(ny) * es);
+        L.src = take(static_cast<size_t>(nx) * ps);
+        L.src_y = take(static_cast<size_t>(ny) * ps);
     }
     L.total = off;
     return L;
@@ -85,7 +97,7 @@ bool grid_ok(const btrt_grid_t* g)
 {
     if (!g) return false;
     if (g->nx < 1 || g->ny < 1) return false;
-    if (g->precision != BTRT_F64 && g->precision != BTRT_F32) return false;
+    if (g->precision < BTRT_F64 || g->precision > BTRT_BF16DEV) return false;
     const int64_t pitch = pitch_for(g->nx, g->precision);
     // Node and in-plane indices are 32-bit in the kernels.
     if (static_cast<int64_t>(g->nx) * g->ny > INT32_MAX) return false;
@@ -98,8 +110,9 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
 {
     if (!grid || !B || !K || !D || !bc || !relax) return fail(BTRT_E_INVAL, "NULL argument");
     if (grid->nx < 1 || grid->ny < 1) return fail(BTRT_E_INVAL, "grid %d x %d: both sides must be >= 1", grid->nx, grid->ny);
-    if (grid->precision != BTRT_F64 && grid->precision != BTRT_F32)
-        return fail(BTRT_E_INVAL, "precision %d is not BTRT_F64 or BTRT_F32", grid->precision);
+    if (grid->precision < BTRT_F64 || grid->precision > BTRT_BF16DEV)
+        return fail(BTRT_E_INVAL, "precision %d is not one of BTRT_F64, BTRT_F32, BTRT_F16DEV, BTRT_BF16DEV",
+                    grid->precision);
     if (!grid_ok(grid)) return fail(BTRT_E_INVAL, "grid %d x %d exceeds 2^31 - 1 nodes", grid->nx, grid->ny);
     for (int a = 0; a < 2; ++a)
         if (!is_finite(B->a[a]) || !is_finite(B->b[a])) return fail(BTRT_E_INVAL, "non-finite flux coefficient");
@@ -180,8 +193,9 @@ void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_
     info->k0 = r.k0;
     info->workspace_bytes = layout_for(g->nx, g->ny, g->precision, src_kind).total;
     // 9 population reads + 9 writes + phi(t-1) read + phi(t) write, plus a per-node source.
-    const double es = g->precision == BTRT_F64 ? 8.0 : 4.0;
-    info->bytes_per_node_launch = (20.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * es;
+    const double es = static_cast<double>(pop_bytes(g->precision));
+    const double ps = g->precision == BTRT_F64 ? 8.0 : 4.0;
+    info->bytes_per_node_launch = 18.0 * es + (2.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * ps;
     info->step = 0;
 }
 
@@ -237,9 +251,12 @@ void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const bt
     a.src_amp = static_cast<T>(R && R->kind == BTRT_SRC_SIN ? R->amp : 0.0);
     a.src = I.kind == kSrcNone ? nullptr : reinterpret_cast<const T*>(I.mem + I.L.src);
     a.src_y = I.kind == kSrcSep ? reinterpret_cast<const T*>(I.mem + I.L.src_y) : nullptr;
-    // Non-temporal stores once the two population buffers exceed the 256 MB Infinity Cache.
-    const double state_bytes = 2.0 * 10.0 * static_cast<double>(I.plane) * sizeof(T);
+    // Non-temporal stores once the two buffers of populations and phi exceed the 256 MB
+    // Infinity Cache.
+    const double state_bytes = 2.0 * static_cast<double>(I.plane) * (9.0 * pop_bytes(I.precision) + sizeof(T));
     a.nts = state_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
+    a.dev_scale = static_cast<T>(I.dev_scale);
+    a.dev_inv = static_cast<T>(1.0 / I.dev_scale);
 }
 
 }  // namespace
@@ -268,7 +285,7 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         return fail(BTRT_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
 
     const size_t nn = static_cast<size_t>(I.nx) * I.ny;
-    const size_t es = I.precision == BTRT_F64 ? 8 : 4;
+    const size_t es = I.precision == BTRT_F64 ? 8 : 4;  // source values
     double* tmp = reinterpret_cast<double*>(mem + I.L.tmp);
     hipError_t err;
     // Source of Eq. (8): a per-node field, or separable sin tables at cell centres.
@@ -289,7 +306,7 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         std::vector<float> fx, fy;
         const void* px = sx.data();
         const void* py = sy.data();
-        if (I.precision == BTRT_F32) {
+        if (I.precision != BTRT_F64) {
             fx.assign(sx.begin(), sx.end());
             fy.assign(sy.begin(), sy.end());
             px = fx.data();
@@ -300,6 +317,18 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) return hip_fail(err, "source table upload");
     }
+    // 16-bit deviation formats: a power-of-two scale that maps the initial magnitude of phi
+    // (and of the wall values) to 2^14, far inside the FP16 range; deviations from
+    // equilibrium are much smaller than phi.
+    I.dev_scale = 1.0;
+    if (I.precision == BTRT_F16DEV || I.precision == BTRT_BF16DEV) {
+        double m = 0.0;
+        for (size_t k = 0; k < nn; ++k) m = std::max(m, std::fabs(phi0[k]));
+        for (int q = 0; q < 4; ++q) m = std::max(m, std::fabs(I.wall[q]));
+        int ex = 0;
+        std::frexp(m > 0.0 ? m : 1.0, &ex);
+        I.dev_scale = std::ldexp(1.0, 14 - ex);
+    }
     if (I.precision == BTRT_F64)
         fill_constants<double>(I, I.a64, B, K, R, r);
     else
@@ -307,14 +336,13 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
 
     err = hipMemcpyAsync(tmp, phi0, nn * sizeof(double), hipMemcpyHostToDevice, s);
     if (err != hipSuccess) return hip_fail(err, "phi0 upload");
+    // The init kernel writes through a sweep's outputs: parity 1 outputs are f[0] and phi[0].
     if (I.precision == BTRT_F64)
-        err = launch_init<double>(nullptr, reinterpret_cast<double*>(mem + I.L.f[0]),
-                                  reinterpret_cast<double*>(mem + I.L.phi[0]), tmp, I.plane, I.nx, I.ny, I.pitch,
-                                  I.perx, I.pery, I.wall, B->a[0], B->a[1], B->b[0], B->b[1], s);
+        err = launch_init<double>(sweep_args<double>(I, 1), kFmtPlain, tmp, I.wall, B->a[0], B->a[1], B->b[0],
+                                  B->b[1], s);
     else
-        err = launch_init<float>(nullptr, reinterpret_cast<float*>(mem + I.L.f[0]),
-                                 reinterpret_cast<float*>(mem + I.L.phi[0]), tmp, I.plane, I.nx, I.ny, I.pitch,
-                                 I.perx, I.pery, I.wall, B->a[0], B->a[1], B->b[0], B->b[1], s);
+        err = launch_init<float>(sweep_args<float>(I, 1), format_of(I.precision), tmp, I.wall, B->a[0], B->a[1],
+                                 B->b[0], B->b[1], s);
     if (err != hipSuccess) return hip_fail(err, "init launch");
     err = hipMemcpyAsync(mem + I.L.snap, tmp, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (err != hipSuccess) return hip_fail(err, "snapshot copy");
@@ -343,14 +371,7 @@ template <typename T>
 GatherArgs<T> gather_args(const Instance& I)
 {
     GatherArgs<T> g{};
-    g.fin = reinterpret_cast<const T*>(I.mem + I.L.f[I.cur]);
-    g.plane = I.plane;
-    g.nx = I.nx;
-    g.ny = I.ny;
-    g.pitch = I.pitch;
-    g.perx = I.perx;
-    g.pery = I.pery;
-    for (int q = 0; q < 4; ++q) g.wall[q] = static_cast<T>(I.wall[q]);
+    g.s = sweep_args<T>(I, I.cur);
     g.snap = reinterpret_cast<double*>(I.mem + I.L.snap);
     g.ref = reinterpret_cast<const double*>(I.mem + I.L.tmp);
     g.out = reinterpret_cast<double*>(I.mem + I.L.tmp);
@@ -368,9 +389,10 @@ int instance_launch(Instance& I, int steps, hipStream_t s)
 {
     hipError_t e;
     if (I.precision == BTRT_F64)
-        e = launch_sweep<double>(sweep_args<double>(I, I.cur), I.kind, I.k1_per_node, steps, s);
+        e = launch_sweep<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, steps, s);
     else
-        e = launch_sweep<float>(sweep_args<float>(I, I.cur), I.kind, I.k1_per_node, steps, s);
+        e = launch_sweep<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, steps,
+                                s);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     I.cur ^= 1;
     I.step += steps;
@@ -380,8 +402,9 @@ int instance_launch(Instance& I, int steps, hipStream_t s)
 int instance_reduce_async(Instance& I, int mode, hipStream_t s)
 {
     double* result = reinterpret_cast<double*>(I.mem + I.L.result);
-    hipError_t e = I.precision == BTRT_F64 ? launch_reduce<double>(gather_args<double>(I), mode, result, s)
-                                           : launch_reduce<float>(gather_args<float>(I), mode, result, s);
+    hipError_t e = I.precision == BTRT_F64
+                       ? launch_reduce<double>(gather_args<double>(I), kFmtPlain, mode, result, s)
+                       : launch_reduce<float>(gather_args<float>(I), format_of(I.precision), mode, result, s);
     return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "reduce launch");
 }
 
@@ -398,11 +421,11 @@ int instance_gather(Instance& I, int population, double* host_out, hipStream_t s
     if (I.precision == BTRT_F64) {
         GatherArgs<double> g = gather_args<double>(I);
         g.population = population;
-        e = launch_gather_field<double>(g, s);
+        e = launch_gather_field<double>(g, kFmtPlain, s);
     } else {
         GatherArgs<float> g = gather_args<float>(I);
         g.population = population;
-        e = launch_gather_field<float>(g, s);
+        e = launch_gather_field<float>(g, format_of(I.precision), s);
     }
     if (e != hipSuccess) return hip_fail(e, "gather launch");
     e = hipMemcpyAsync(host_out, I.mem + I.L.tmp, nn * sizeof(double), hipMemcpyDeviceToHost, s);

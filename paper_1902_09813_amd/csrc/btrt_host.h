@@ -16,6 +16,9 @@ namespace btrth {
 
 using btrtk::GatherArgs;
 using btrtk::SweepArgs;
+using btrtk::kFmtPlain;
+using btrtk::kFmtF16Dev;
+using btrtk::kFmtBF16Dev;
 
 // Error reporting: sets the calling thread's last-error message and returns code.
 int fail(int code, const char* fmt, ...);
@@ -28,6 +31,9 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Row pitch (elements) of the device planes: rows start on 256-byte boundaries.
 int pitch_for(int nx, int precision);
+// Bytes of one stored population value; kernel storage format of a precision.
+size_t pop_bytes(int precision);
+int format_of(int precision);
 
 // Byte offsets of every buffer of one instance inside its memory region.
 struct Layout {
@@ -63,6 +69,7 @@ struct Instance {
     Layout L{};
     int cur = 0;
     int64_t step = 0;
+    double dev_scale = 1.0;   // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq))
     SweepArgs<double> a64{};  // problem constants; buffer pointers are set per launch
     SweepArgs<float> a32{};
     btrt_info_t info{};

@@ -33,18 +33,20 @@ struct SweepArgs {
     T K11, K12, K22;   // K1 of Eq. (30) when A is constant
     T k0, k2xx, k2xy, k2yy;
     T src_amp;
+    T dev_scale, dev_inv; // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq)), f+ = f_eq + h dev_inv
     int tiles_x, tiles_y; // set by the launcher for the kernel it picks
     int nts;              // 1: non-temporal stores (grids much larger than the caches)
 };
 
-// Gather-reduce of phi(t) (for the residual, error norms, field and population reads).
+// Storage formats of the post-collision populations (kernels' template selector).
+enum Format : int { kFmtPlain = 0, kFmtF16Dev = 1, kFmtBF16Dev = 2 };
+
+// Gather-reduce of phi(t) (for the residual, error norms, field and population reads): the
+// sweep arguments of the current state (fin / phi_prev = the buffers holding f+(t-1) and
+// phi(t-1)) plus the reduction buffers.
 template <typename T>
 struct GatherArgs {
-    const T* fin;      // post-collision populations f+(t-1)
-    int64_t plane;
-    int nx, ny, pitch;
-    int perx, pery;
-    T wall[4];
+    SweepArgs<T> s;
     double* snap;      // kResidual: phi snapshot (dense nx*ny, FP64), updated in place
     const double* ref; // kError: reference (dense nx*ny)
     double* out;       // dense nx*ny output for field / population reads
@@ -65,28 +67,28 @@ constexpr int kReducePartials = 6; // sum a, sum b, sum c, sum d, max, non-finit
 constexpr int kReduceBlocks = 1024;
 constexpr int kBlock = 256;
 
-// Launchers (defined in btrt_kernels.hip). They return the launch's hipError_t.
+// Launchers (defined in btrt_kernels.hip). They return the launch's hipError_t. fmt selects
+// the storage format (kFmtPlain for double; any for float).
 // steps: 1 (one time step) or 2 (two fused time steps through LDS).
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int src_kind, bool k1_per_node, int steps, hipStream_t s);
-// All instances of a batch advance `steps` (1 or 2) time steps in one launch of `grid`
-// blocks (0: one block per tile) walking the concatenated tile list.
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, int steps, hipStream_t s);
+// f+(-1) and phi(-1) := phi0 into a.fin / a.phi_prev (see init_values); FP64 arithmetic.
+template <typename T>
+hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,
+                       double bx, double by, hipStream_t s);
+template <typename T>
+hipError_t launch_gather_field(const GatherArgs<T>& a, int fmt, hipStream_t s);
+template <typename T>
+hipError_t launch_reduce(const GatherArgs<T>& a, int fmt, int mode, double* result, hipStream_t s);
+template <typename T>
+hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, hipStream_t s);
+// All instances of a batch (plain storage) advance `steps` (1 or 2) time steps in one launch of
+// `grid` blocks (0: one block per tile) walking the concatenated tile list.
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
                               int flip, int steps, int grid, hipStream_t s);
 // Tile height of the kernel that fuses `steps` steps (tile width is 64).
 int tile_rows(int steps, int precision_bytes);
 constexpr int kTileWidth = 64;
-
-template <typename T>
-hipError_t launch_init(const T* dummy, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx,
-                       int ny, int pitch, int perx, int pery, const double wall[4], double ax,
-                       double ay, double bx, double by, hipStream_t s);
-template <typename T>
-hipError_t launch_gather_field(const GatherArgs<T>& a, hipStream_t s);
-template <typename T>
-hipError_t launch_reduce(const GatherArgs<T>& a, int mode, double* result, hipStream_t s);
-template <typename T>
-hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, hipStream_t s);
 
 }  // namespace btrtk

@@ -2,7 +2,7 @@
 //
 // State between steps: the post-collision populations f+(t-1) in 9 SoA planes
 // (f[i][y][pitch], i in the velocity order of Eq. (85)) and phi(t-1) in one plane.
-// One sweep per time step, one thread per node:
+// One node update:
 //   1. pull  f_i(x, t) = f_i+(x - c_i, t-1)                         (Eq. (38))
 //      or, when x - c_i lies beyond a Dirichlet wall,
 //            f_i(x, t) = -f_opp(i)+(x, t-1) + 2 w_i phi_w             (Eqs. (54)-(56))
@@ -13,6 +13,10 @@
 // Reads and writes are disjoint (two population buffers), so no synchronisation is needed.
 // The 9x9 transform is a handful of adds per node and stays in registers: the sweep is
 // bound by HBM bandwidth, not by arithmetic, so there is no matrix-core work here.
+//
+// Storage formats: plain FP64 or FP32 planes, or 16-bit planes (FP16 or BF16) of scaled
+// deviations from equilibrium, h_i = q(s (f_i+ - f_i^eq(phi))), with phi(t) in FP32 at the
+// same node (the phi plane the sweep writes anyway) and FP32 arithmetic.
 
 #include "btrt_internal.h"
 #include "btrt_node.h"
@@ -56,30 +60,103 @@ __device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int 
     return T(0);
 }
 
+// ---- storage formats ---------------------------------------------------------------------
+// pull(a, x, y, f): f_i(x, t) from the stored f+(t-1) (with wrap / bounce-back);
+// settle(a, f, phi): f+ as the next pull will see it (identity, or the 16-bit round trip);
+// put(a, n, f, phi): store f+(t) and phi(t) at node index n.
+
+template <typename T_>
+struct Plain {
+    using T = T_;
+    __device__ static void pull(const SweepArgs<T>& a, int x, int y, T f[9])
+    {
+        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
+    }
+    __device__ static void settle(const SweepArgs<T>&, T*, T) {}
+    __device__ static void put(const SweepArgs<T>& a, int n, const T f[9], T phi)
+    {
+        const int64_t p = a.plane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, f[i], a.nts);
+        store(a.phi_out + n, phi, a.nts);
+    }
+};
+
+// IEEE binary16, round to nearest even.
+struct F16Codec {
+    __device__ static unsigned short enc(float v) { return __builtin_bit_cast(unsigned short, static_cast<_Float16>(v)); }
+    __device__ static float dec(unsigned short h) { return static_cast<float>(__builtin_bit_cast(_Float16, h)); }
+};
+
+// bfloat16 (the upper half of an FP32), round to nearest even.
+struct BF16Codec {
+    __device__ static unsigned short enc(float v)
+    {
+        unsigned u = __builtin_bit_cast(unsigned, v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);  // NaN stays NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return static_cast<unsigned short>(u >> 16);
+    }
+    __device__ static float dec(unsigned short h) { return __builtin_bit_cast(float, static_cast<unsigned>(h) << 16); }
+};
+
+template <typename C>
+struct Dev {
+    using T = float;
+    __device__ static float rebuild(const SweepArgs<float>& a, int i, float phi, unsigned short h)
+    {
+        return fmadd(C::dec(h), a.dev_inv, feq_dir(i, phi, a.ax, a.ay, a.bx, a.by));
+    }
+    __device__ static unsigned short quant(const SweepArgs<float>& a, int i, float f, float phi)
+    {
+        return C::enc((f - feq_dir(i, phi, a.ax, a.ay, a.bx, a.by)) * a.dev_scale);
+    }
+    __device__ static void pull(const SweepArgs<float>& a, int x, int y, float f[9])
+    {
+        const unsigned short* __restrict__ H = reinterpret_cast<const unsigned short*>(a.fin);
+        const float* __restrict__ P = a.phi_prev;
+        const int64_t p = a.plane;
+        gather_with<float>([&](int i, int idx) { return rebuild(a, i, P[idx], H[i * p + idx]); }, x, y, a.nx, a.ny,
+                           a.pitch, a.perx, a.pery, a.wall, f);
+    }
+    __device__ static void settle(const SweepArgs<float>& a, float f[9], float phi)
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = rebuild(a, i, phi, quant(a, i, f[i], phi));
+    }
+    __device__ static void put(const SweepArgs<float>& a, int n, const float f[9], float phi)
+    {
+        unsigned short* __restrict__ H = reinterpret_cast<unsigned short*>(a.fout);
+        const int64_t p = a.plane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) store(H + i * p + n, quant(a, i, f[i], phi), a.nts);
+        store(a.phi_out + n, phi, a.nts);
+    }
+};
+
+// ---- one time step --------------------------------------------------------------------------
+
 // One time step on tile (tx, ty) of kTileX x kTileY nodes, one node per thread.
-template <typename T, int SRC, bool KPHI>
-__device__ __forceinline__ void tile1(const SweepArgs<T>& a, int tx, int ty)
+template <typename F, int SRC, bool KPHI>
+__device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx, int ty)
 {
+    using T = typename F::T;
     const int x = tx * kTileX + static_cast<int>(threadIdx.x % kTileX);
     const int y = ty * kTileY + static_cast<int>(threadIdx.x / kTileX);
     if (x >= a.nx || y >= a.ny) return;
-
     T f[9];
-    gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
+    F::pull(a, x, y, f);
     const int n = y * a.pitch + x;
     const T phi = collide<T, SRC, KPHI>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y));
-    const int64_t p = a.plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, f[i], a.nts);
-    store(a.phi_out + n, phi, a.nts);
+    F::put(a, n, f, phi);
 }
 
-template <typename T, int SRC, bool KPHI>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<T> a)
+template <typename F, int SRC, bool KPHI>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename F::T> a)
 {
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
-    tile1<T, SRC, KPHI>(a, tile - ty * a.tiles_x, ty);
+    tile1<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty);
 }
 
 // Wrap a coordinate of a periodic direction into [0, n) (any distance).
@@ -89,12 +166,12 @@ __device__ __forceinline__ int wrap(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// Two time steps per launch over a kTile2X x TY2 tile. Step 1 runs on the tile plus a
-// one-node ring, pulling f+(t-1) from global memory, and leaves f+(t) and phi(t) in LDS;
-// step 2 runs on the tile, pulling f+(t) from LDS (bounce-back at Dirichlet walls uses the
-// node's own LDS values), and stores f+(t+1) and phi(t+1). Every node update is the same
-// gather/collide arithmetic as in sweep_kernel, so results are bitwise identical to two
-// single steps; HBM traffic per node update is halved.
+// ---- two time steps per launch --------------------------------------------------------------
+// Step 1 runs on a kTile2X x TY tile plus a one-node ring, pulling f+(t-1) from global memory,
+// and leaves f+(t) (as the next pull would see it) and phi(t) in LDS; step 2 runs on the tile,
+// pulling f+(t) from LDS (bounce-back at Dirichlet walls uses the node's own LDS values), and
+// stores f+(t+1) and phi(t+1). Every node update is the same arithmetic as in sweep_kernel, so
+// results are bitwise identical to two single steps; HBM traffic per node update is halved.
 constexpr int kTile2X = 64;
 constexpr int kBlock2 = 512;
 
@@ -106,10 +183,12 @@ struct Tile2 {
     static constexpr int S2 = (kTile2X * TY + kBlock2 - 1) / kBlock2;
 };
 
-template <typename T, int SRC, bool KPHI>
-__device__ __forceinline__ void tile2(const SweepArgs<T>& a, int tx, int ty, T (&lf)[9][Tile2<T>::E],
-                                      T (&lphi)[Tile2<T>::E])
+template <typename F, int SRC, bool KPHI>
+__device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx, int ty,
+                                      typename F::T (&lf)[9][Tile2<typename F::T>::E],
+                                      typename F::T (&lphi)[Tile2<typename F::T>::E])
 {
+    using T = typename F::T;
     using G = Tile2<T>;
     constexpr int TX = kTile2X, TY = G::TY, EX = G::EX, E = G::E;
     const int nx = a.nx, ny = a.ny;
@@ -136,7 +215,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<T>& a, int tx, int ty, T (
         gxs[j] = gx;
         gys[j] = gy;
         if (e) {
-            gather(a.fin, a.plane, gx, gy, nx, ny, a.pitch, a.perx, a.pery, a.wall, f[j]);
+            F::pull(a, gx, gy, f[j]);
             pp[j] = a.phi_prev[gy * a.pitch + gx];
         }
     }
@@ -146,6 +225,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<T>& a, int tx, int ty, T (
         const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
         const int n = gys[j] * a.pitch + gxs[j];
         const T phi = collide<T, SRC, KPHI>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j]));
+        F::settle(a, f[j], phi);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lf[i][s] = f[j][i];
         lphi[s] = phi;
@@ -176,21 +256,19 @@ __device__ __forceinline__ void tile2(const SweepArgs<T>& a, int tx, int ty, T (
         g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
         const int n = gy * a.pitch + gx;
         const T phi = collide<T, SRC, KPHI>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy));
-        const int64_t p = a.plane;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) store(a.fout + i * p + n, g[i], a.nts);
-        store(a.phi_out + n, phi, a.nts);
+        F::put(a, n, g, phi);
     }
 }
 
-template <typename T, int SRC, bool KPHI>
-__global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<T> a)
+template <typename F, int SRC, bool KPHI>
+__global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<typename F::T> a)
 {
+    using T = typename F::T;
     __shared__ T lf[9][Tile2<T>::E];
     __shared__ T lphi[Tile2<T>::E];
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
-    tile2<T, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, lf, lphi);
+    tile2<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, lf, lphi);
 }
 
 // ---- many instances in one launch -------------------------------------------------------
@@ -215,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __r
                                                         const int* __restrict__ begin, const int* __restrict__ par,
                                                         int ninst, int total, int flip)
 {
+    using F = Plain<T>;
     const int g = static_cast<int>(gridDim.x);
     for (int t = xcd_tile(); t < total; t += g) {
         const int i = owner(begin, ninst, t);
@@ -223,12 +302,12 @@ __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __r
         const int tiles_x = (a.nx + kTileX - 1) / kTileX;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile1<T, kSrcNone, false>(a, tx, ty); break;
-            case 1: tile1<T, kSrcNone, true>(a, tx, ty); break;
-            case 2: tile1<T, kSrcField, false>(a, tx, ty); break;
-            case 3: tile1<T, kSrcField, true>(a, tx, ty); break;
-            case 4: tile1<T, kSrcSep, false>(a, tx, ty); break;
-            default: tile1<T, kSrcSep, true>(a, tx, ty); break;
+            case 0: tile1<F, kSrcNone, false>(a, tx, ty); break;
+            case 1: tile1<F, kSrcNone, true>(a, tx, ty); break;
+            case 2: tile1<F, kSrcField, false>(a, tx, ty); break;
+            case 3: tile1<F, kSrcField, true>(a, tx, ty); break;
+            case 4: tile1<F, kSrcSep, false>(a, tx, ty); break;
+            default: tile1<F, kSrcSep, true>(a, tx, ty); break;
         }
     }
 }
@@ -238,6 +317,7 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
                                                          const int* __restrict__ begin, const int* __restrict__ par,
                                                          int ninst, int total, int flip)
 {
+    using F = Plain<T>;
     __shared__ T lf[9][Tile2<T>::E];
     __shared__ T lphi[Tile2<T>::E];
     const int g = static_cast<int>(gridDim.x);
@@ -248,31 +328,36 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
         const int tiles_x = (a.nx + kTile2X - 1) / kTile2X;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile2<T, kSrcNone, false>(a, tx, ty, lf, lphi); break;
-            case 1: tile2<T, kSrcNone, true>(a, tx, ty, lf, lphi); break;
-            case 2: tile2<T, kSrcField, false>(a, tx, ty, lf, lphi); break;
-            case 3: tile2<T, kSrcField, true>(a, tx, ty, lf, lphi); break;
-            case 4: tile2<T, kSrcSep, false>(a, tx, ty, lf, lphi); break;
-            default: tile2<T, kSrcSep, true>(a, tx, ty, lf, lphi); break;
+            case 0: tile2<F, kSrcNone, false>(a, tx, ty, lf, lphi); break;
+            case 1: tile2<F, kSrcNone, true>(a, tx, ty, lf, lphi); break;
+            case 2: tile2<F, kSrcField, false>(a, tx, ty, lf, lphi); break;
+            case 3: tile2<F, kSrcField, true>(a, tx, ty, lf, lphi); break;
+            case 4: tile2<F, kSrcSep, false>(a, tx, ty, lf, lphi); break;
+            default: tile2<F, kSrcSep, true>(a, tx, ty, lf, lphi); break;
         }
         __syncthreads();  // the next tile reuses the LDS
     }
 }
 
-// f+(-1) such that the first pull yields f(0) = f^eq(phi0) (Section 4 initialisation).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void init_kernel(T* __restrict__ f, T* __restrict__ phi_prev,
-                                                      const double* __restrict__ phi0, int64_t plane,
-                                                      int nx, int ny, int pitch, int perx, int pery,
-                                                      double w0, double w1, double w2, double w3,
-                                                      double ax, double ay, double bx, double by)
+// ---- set-up, field reads and reductions -------------------------------------------------
+
+// f+(-1) such that the first pull yields f(0) = f^eq(phi0) (Section 4 initialisation), and
+// phi(-1) := phi0; written through the format's put into a.fout / a.phi_out.
+template <typename F>
+__global__ __launch_bounds__(kBlock) void init_kernel(SweepArgs<typename F::T> a, const double* __restrict__ phi0,
+                                                      double w0, double w1, double w2, double w3, double ax,
+                                                      double ay, double bx, double by)
 {
+    using T = typename F::T;
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= static_cast<int64_t>(nx) * ny) return;
-    const int y = static_cast<int>(k / nx);
-    const int x = static_cast<int>(k - static_cast<int64_t>(y) * nx);
+    if (k >= static_cast<int64_t>(a.nx) * a.ny) return;
+    const int y = static_cast<int>(k / a.nx);
+    const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.nx);
     const double wall[4] = {w0, w1, w2, w3};
-    init_node(f, phi_prev, phi0, plane, x, y, nx, ny, pitch, perx, pery, wall, ax, ay, bx, by);
+    T f[9];
+    init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, wall, ax, ay, bx, by,
+                [&](int i, double v) { f[i] = static_cast<T>(v); });
+    F::put(a, y * a.pitch + x, f, static_cast<T>(phi0[k]));
 }
 
 template <typename T>
@@ -287,15 +372,16 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(const double* __restric
 }
 
 // phi(t) (or one population f_i(t)) at every node into a dense FP64 array.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void gather_field_kernel(GatherArgs<T> a)
+template <typename F>
+__global__ __launch_bounds__(kBlock) void gather_field_kernel(GatherArgs<typename F::T> a)
 {
+    using T = typename F::T;
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= static_cast<int64_t>(a.nx) * a.ny) return;
-    const int y = static_cast<int>(k / a.nx);
-    const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.nx);
+    if (k >= static_cast<int64_t>(a.s.nx) * a.s.ny) return;
+    const int y = static_cast<int>(k / a.s.nx);
+    const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.s.nx);
     T f[9];
-    gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
+    F::pull(a.s, x, y, f);
     T v = T(0);
     if (a.population < 0) {
         v = sum9(f);
@@ -342,17 +428,18 @@ __device__ __forceinline__ void block_reduce(double v[kReducePartials])
 // First pass: each block covers a fixed grid-stride subset of the nodes and writes its
 // partial sums. kResidual: a = |phi - snap|, b = |phi|, snap := phi (Eq. (64)).
 // kError: a = |phi - ref|, b = |ref|, c = (phi - ref)^2, d = ref^2, max |phi - ref| (Eq. (63)).
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void reduce_kernel(GatherArgs<T> a)
+template <typename F, int MODE>
+__global__ __launch_bounds__(kBlock) void reduce_kernel(GatherArgs<typename F::T> a)
 {
+    using T = typename F::T;
     double v[kReducePartials] = {0, 0, 0, 0, 0, 0};
-    const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
+    const int64_t nn = static_cast<int64_t>(a.s.nx) * a.s.ny;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; k < nn; k += stride) {
-        const int y = static_cast<int>(k / a.nx);
-        const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.nx);
+        const int y = static_cast<int>(k / a.s.nx);
+        const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.s.nx);
         T f[9];
-        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
+        F::pull(a.s, x, y, f);
         const double phi = static_cast<double>(sum9(f));
         if (!isfinite(phi)) v[5] += 1.0;
         if constexpr (MODE == kResidual) {
@@ -389,13 +476,11 @@ __global__ __launch_bounds__(kBlock) void reduce_final_kernel(const double* __re
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
-}  // namespace
-
-template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a_in, int src_kind, bool k1_per_node, int steps, hipStream_t s)
+template <typename F>
+hipError_t sweep_with(const SweepArgs<typename F::T>& a_in, int src_kind, bool k1_per_node, int steps, hipStream_t s)
 {
+    using T = typename F::T;
     SweepArgs<T> a = a_in;
-    unsigned grid;
     if (steps == 2) {
         a.tiles_x = (a.nx + kTile2X - 1) / kTile2X;
         a.tiles_y = (a.ny + Tile2<T>::TY - 1) / Tile2<T>::TY;
@@ -403,13 +488,13 @@ hipError_t launch_sweep(const SweepArgs<T>& a_in, int src_kind, bool k1_per_node
         a.tiles_x = (a.nx + kTileX - 1) / kTileX;
         a.tiles_y = (a.ny + kTileY - 1) / kTileY;
     }
-    grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
+    const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
 #define BTRT_SWEEP(SRC, KP)                                                                                \
     do {                                                                                                   \
         if (steps == 2)                                                                                    \
-            hipLaunchKernelGGL((sweep2_kernel<T, SRC, KP>), dim3(grid), dim3(kBlock2), 0, s, a);          \
+            hipLaunchKernelGGL((sweep2_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock2), 0, s, a);          \
         else                                                                                               \
-            hipLaunchKernelGGL((sweep_kernel<T, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);            \
+            hipLaunchKernelGGL((sweep_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);            \
     } while (0)
     if (k1_per_node) {
         if (src_kind == kSrcField) BTRT_SWEEP(kSrcField, true);
@@ -423,6 +508,81 @@ hipError_t launch_sweep(const SweepArgs<T>& a_in, int src_kind, bool k1_per_node
 #undef BTRT_SWEEP
     return hipGetLastError();
 }
+
+template <typename F>
+hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], double ax, double ay,
+                     double bx, double by, hipStream_t s)
+{
+    const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
+    hipLaunchKernelGGL((init_kernel<F>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a, phi0, wall[0], wall[1], wall[2],
+                       wall[3], ax, ay, bx, by);
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t gather_with_fmt(const GatherArgs<typename F::T>& a, hipStream_t s)
+{
+    const int64_t nn = static_cast<int64_t>(a.s.nx) * a.s.ny;
+    hipLaunchKernelGGL((gather_field_kernel<F>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t reduce_with(const GatherArgs<typename F::T>& a, int mode, double* result, hipStream_t s)
+{
+    const int64_t nn = static_cast<int64_t>(a.s.nx) * a.s.ny;
+    const unsigned nb = static_cast<unsigned>(std::min<int64_t>(kReduceBlocks, (nn + kBlock - 1) / kBlock));
+    if (mode == kResidual)
+        hipLaunchKernelGGL((reduce_kernel<F, kResidual>), dim3(nb), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((reduce_kernel<F, kError>), dim3(nb), dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kBlock), 0, s, a.partial, static_cast<int>(nb), result);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Format dispatch: double has only the plain format; float has plain, FP16 and BF16 deviations.
+#define BTRT_BY_FORMAT(T, FN, ...)                                                                       \
+    do {                                                                                                 \
+        if constexpr (sizeof(T) == 8) {                                                                  \
+            if (fmt != kFmtPlain) return hipErrorInvalidValue;                                           \
+            return FN<Plain<T>>(__VA_ARGS__);                                                            \
+        } else {                                                                                         \
+            if (fmt == kFmtF16Dev) return FN<Dev<F16Codec>>(__VA_ARGS__);                                \
+            if (fmt == kFmtBF16Dev) return FN<Dev<BF16Codec>>(__VA_ARGS__);                              \
+            return FN<Plain<T>>(__VA_ARGS__);                                                            \
+        }                                                                                                \
+    } while (0)
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, int steps, hipStream_t s)
+{
+    BTRT_BY_FORMAT(T, sweep_with, a, src_kind, k1_per_node, steps, s);
+}
+
+template <typename T>
+hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,
+                       double bx, double by, hipStream_t s)
+{
+    BTRT_BY_FORMAT(T, init_with, a, phi0, wall, ax, ay, bx, by, s);
+}
+
+template <typename T>
+hipError_t launch_gather_field(const GatherArgs<T>& a, int fmt, hipStream_t s)
+{
+    BTRT_BY_FORMAT(T, gather_with_fmt, a, s);
+}
+
+template <typename T>
+hipError_t launch_reduce(const GatherArgs<T>& a, int fmt, int mode, double* result, hipStream_t s)
+{
+    BTRT_BY_FORMAT(T, reduce_with, a, mode, result, s);
+}
+
+#undef BTRT_BY_FORMAT
 
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
@@ -444,40 +604,6 @@ int tile_rows(int steps, int precision_bytes)
 }
 
 template <typename T>
-hipError_t launch_init(const T*, T* f, T* phi_prev, const double* phi0, int64_t plane, int nx, int ny,
-                       int pitch, int perx, int pery, const double wall[4], double ax, double ay,
-                       double bx, double by, hipStream_t s)
-{
-    const int64_t nn = static_cast<int64_t>(nx) * ny;
-    hipLaunchKernelGGL((init_kernel<T>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, f, phi_prev, phi0, plane,
-                       nx, ny, pitch, perx, pery, wall[0], wall[1], wall[2], wall[3], ax, ay, bx, by);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_gather_field(const GatherArgs<T>& a, hipStream_t s)
-{
-    const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
-    hipLaunchKernelGGL((gather_field_kernel<T>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_reduce(const GatherArgs<T>& a, int mode, double* result, hipStream_t s)
-{
-    const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
-    const unsigned nb = static_cast<unsigned>(std::min<int64_t>(kReduceBlocks, (nn + kBlock - 1) / kBlock));
-    if (mode == kResidual)
-        hipLaunchKernelGGL((reduce_kernel<T, kResidual>), dim3(nb), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((reduce_kernel<T, kError>), dim3(nb), dim3(kBlock), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kBlock), 0, s, a.partial, static_cast<int>(nb), result);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, hipStream_t s)
 {
     const int64_t nn = static_cast<int64_t>(nx) * ny;
@@ -485,13 +611,13 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
     return hipGetLastError();
 }
 
-#define BTRT_INSTANTIATE(T)                                                                                  \
-    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, bool, int, hipStream_t);                  \
-    template hipError_t launch_init<T>(const T*, T*, T*, const double*, int64_t, int, int, int, int, int,    \
-                                       const double[4], double, double, double, double, hipStream_t);        \
-    template hipError_t launch_gather_field<T>(const GatherArgs<T>&, hipStream_t);                          \
-    template hipError_t launch_reduce<T>(const GatherArgs<T>&, int, double*, hipStream_t);                  \
-    template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);                     \
+#define BTRT_INSTANTIATE(T)                                                                                        \
+    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, bool, int, hipStream_t);                   \
+    template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], double, double,   \
+                                       double, double, hipStream_t);                                               \
+    template hipError_t launch_gather_field<T>(const GatherArgs<T>&, int, hipStream_t);                           \
+    template hipError_t launch_reduce<T>(const GatherArgs<T>&, int, int, double*, hipStream_t);                   \
+    template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);                         \
     template hipError_t launch_batch_sweep<T>(const BatchEntry<T>*, const int*, const int*, int, int, int, int, int, \
                                               hipStream_t);
 

@@ -39,31 +39,23 @@ __host__ __device__ inline T wall_value(bool out_x, bool out_y, T vx, T vy)
     return (out_x && out_y) ? T(0.5) * (vx + vy) : (out_x ? vx : vy);
 }
 
-// Pull f_i(x, t) for all nine directions from the post-collision planes of t-1.
-template <typename T>
-__host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane, int x, int y, int nx,
-                                       int ny, int pitch, int perx, int pery, const T* wall, T f[9])
+// Pull f_i(x, t) for all nine directions: load(i, idx) returns the post-collision value
+// f_i+(t-1) stored at in-plane index idx (for a storage format of the caller's choice).
+template <typename T, typename Load>
+__host__ __device__ inline void gather_with(Load load, int x, int y, int nx, int ny, int pitch, int perx, int pery,
+                                            const T* wall, T f[9])
 {
-    const T* __restrict__ F0 = fin;
-    const T* __restrict__ F1 = fin + plane;
-    const T* __restrict__ F2 = fin + 2 * plane;
-    const T* __restrict__ F3 = fin + 3 * plane;
-    const T* __restrict__ F4 = fin + 4 * plane;
-    const T* __restrict__ F5 = fin + 5 * plane;
-    const T* __restrict__ F6 = fin + 6 * plane;
-    const T* __restrict__ F7 = fin + 7 * plane;
-    const T* __restrict__ F8 = fin + 8 * plane;
     const int n = y * pitch + x;
     if (x > 0 && x < nx - 1 && y > 0 && y < ny - 1) {
-        f[0] = F0[n];
-        f[1] = F1[n - 1];
-        f[2] = F2[n - pitch];
-        f[3] = F3[n + 1];
-        f[4] = F4[n + pitch];
-        f[5] = F5[n - pitch - 1];
-        f[6] = F6[n - pitch + 1];
-        f[7] = F7[n + pitch + 1];
-        f[8] = F8[n + pitch - 1];
+        f[0] = load(0, n);
+        f[1] = load(1, n - 1);
+        f[2] = load(2, n - pitch);
+        f[3] = load(3, n + 1);
+        f[4] = load(4, n + pitch);
+        f[5] = load(5, n - pitch - 1);
+        f[6] = load(6, n - pitch + 1);
+        f[7] = load(7, n + pitch + 1);
+        f[8] = load(8, n + pitch - 1);
         return;
     }
     // Edge node: wrap periodic directions, bounce back at Dirichlet walls.
@@ -75,15 +67,44 @@ __host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane,
     if (yp >= ny) { if (pery) yp -= ny; else okyp = false; }
     const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
-    f[0] = F0[n];
-    f[1] = okxm ? F1[r0 + xm] : bounce(F3[n], tw1, wall[0]);
-    f[2] = okym ? F2[rm + x] : bounce(F4[n], tw1, wall[2]);
-    f[3] = okxp ? F3[r0 + xp] : bounce(F1[n], tw1, wall[1]);
-    f[4] = okyp ? F4[rp + x] : bounce(F2[n], tw1, wall[3]);
-    f[5] = (okxm && okym) ? F5[rm + xm] : bounce(F7[n], tw5, wall_value(!okxm, !okym, wall[0], wall[2]));
-    f[6] = (okxp && okym) ? F6[rm + xp] : bounce(F8[n], tw5, wall_value(!okxp, !okym, wall[1], wall[2]));
-    f[7] = (okxp && okyp) ? F7[rp + xp] : bounce(F5[n], tw5, wall_value(!okxp, !okyp, wall[1], wall[3]));
-    f[8] = (okxm && okyp) ? F8[rp + xm] : bounce(F6[n], tw5, wall_value(!okxm, !okyp, wall[0], wall[3]));
+    f[0] = load(0, n);
+    f[1] = okxm ? load(1, r0 + xm) : bounce(load(3, n), tw1, wall[0]);
+    f[2] = okym ? load(2, rm + x) : bounce(load(4, n), tw1, wall[2]);
+    f[3] = okxp ? load(3, r0 + xp) : bounce(load(1, n), tw1, wall[1]);
+    f[4] = okyp ? load(4, rp + x) : bounce(load(2, n), tw1, wall[3]);
+    f[5] = (okxm && okym) ? load(5, rm + xm) : bounce(load(7, n), tw5, wall_value(!okxm, !okym, wall[0], wall[2]));
+    f[6] = (okxp && okym) ? load(6, rm + xp) : bounce(load(8, n), tw5, wall_value(!okxp, !okym, wall[1], wall[2]));
+    f[7] = (okxp && okyp) ? load(7, rp + xp) : bounce(load(5, n), tw5, wall_value(!okxp, !okyp, wall[1], wall[3]));
+    f[8] = (okxm && okyp) ? load(8, rp + xm) : bounce(load(6, n), tw5, wall_value(!okxm, !okyp, wall[0], wall[3]));
+}
+
+// Pull from nine planes of T (plane stride `plane`).
+template <typename T>
+__host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane, int x, int y, int nx,
+                                       int ny, int pitch, int perx, int pery, const T* wall, T f[9])
+{
+    gather_with<T>([fin, plane](int i, int idx) { return fin[i * plane + idx]; }, x, y, nx, ny, pitch, perx, pery,
+                   wall, f);
+}
+
+// Equilibrium of Eq. (7) with D = phi I for direction i: w_i (phi + 3 c_i . B(phi)), with
+// B(phi) = phi (a + b phi / 2).
+template <typename T>
+__host__ __device__ inline T feq_dir(int i, T phi, T ax, T ay, T bx, T by)
+{
+    const T Bx = phi * fmadd(T(0.5) * bx, phi, ax);
+    const T By = phi * fmadd(T(0.5) * by, phi, ay);
+    switch (i) {
+        case 0: return Lat<T>::w0 * phi;
+        case 1: return Lat<T>::w1 * fmadd(T(3), Bx, phi);
+        case 2: return Lat<T>::w1 * fmadd(T(3), By, phi);
+        case 3: return Lat<T>::w1 * fmadd(T(-3), Bx, phi);
+        case 4: return Lat<T>::w1 * fmadd(T(-3), By, phi);
+        case 5: return Lat<T>::w5 * fmadd(T(3), Bx + By, phi);
+        case 6: return Lat<T>::w5 * fmadd(T(3), By - Bx, phi);
+        case 7: return Lat<T>::w5 * fmadd(T(-3), Bx + By, phi);
+        default: return Lat<T>::w5 * fmadd(T(3), Bx - By, phi);
+    }
 }
 
 template <typename T>
@@ -183,20 +204,17 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
 // f+(-1) at node (x, y) such that the first pull yields f(0) = f^eq(phi0) (Section 4): a value
 // whose consumer is an interior pull gets f^eq of Eq. (7) (D = phi I) at its destination; a
 // value whose consumer is the bounce-back rule gets 2 w phi_w - f^eq_opp at its own node.
-// Also phi(-1) := phi0, so the correction G starts at zero.
-template <typename T>
-__host__ __device__ inline void init_node(T* __restrict__ f, T* __restrict__ phi_prev,
-                                          const double* __restrict__ phi0, int64_t plane, int x, int y, int nx,
-                                          int ny, int pitch, int perx, int pery, const double wall[4], double ax,
-                                          double ay, double bx, double by)
+// put(i, v) receives the value for direction i (FP64).
+template <typename Put>
+__host__ __device__ inline void init_values(const double* __restrict__ phi0, int x, int y, int nx, int ny, int perx,
+                                            int pery, const double wall[4], double ax, double ay, double bx,
+                                            double by, Put put)
 {
     constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
     const double wt[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    const int64_t k = static_cast<int64_t>(y) * nx + x;
-    const double here = phi0[k];
-    const int n = y * pitch + x;
+    const double here = phi0[static_cast<int64_t>(y) * nx + x];
     for (int i = 0; i < 9; ++i) {
         int xd = x + cx[i], yd = y + cy[i];
         bool outx = false, outy = false;
@@ -219,9 +237,8 @@ __host__ __device__ inline void init_node(T* __restrict__ f, T* __restrict__ phi
             const double feq_o = wt[o] * (here + 3.0 * (cx[o] * Bx + cy[o] * By));
             v = 2.0 * wt[i] * pw - feq_o;
         }
-        f[i * plane + n] = static_cast<T>(v);
+        put(i, v);
     }
-    phi_prev[n] = static_cast<T>(here);
 }
 
 }  // namespace btrtk

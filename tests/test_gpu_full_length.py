@@ -3,8 +3,10 @@
 The oracle's full runs (1024 x 1024 for 20000 steps, 4096 x 4096 for 5000 steps) take minutes to
 an hour on a CPU, so their results are stored: tests/golden/make_full_length.py (which calls
 only the oracle) wrote phi and all nine populations at 256 sampled nodes plus whole-field norms.
-Tolerance: 1e-12 normwise (the node differences over max|phi| or max|f|), and 1e-12 relative
-on the norms.
+Tolerance: 1e-12 normwise (the node differences over max|phi| or max|f|). The whole-field
+norms are held to what that bound implies for N nodes with |d| <= eps max|phi| at every node:
+|max|phi|| moves by at most eps max|phi|, sum|phi| and sum phi by N eps max|phi|, and sum phi^2
+by 2 eps max|phi| sum|phi| + N (eps max|phi|)^2.
 """
 import json
 import os
@@ -48,8 +50,12 @@ def test_full_length_against_stored_oracle(name, make):
     e_phi = np.max(np.abs(phi[ys, xs] - phi_ref)) / max_phi
     e_f = np.max(np.abs(f[:, ys, xs].T - f_ref)) / max_f
     print(f"    sampled normwise phi {e_phi:.3e}  f {e_f:.3e}", flush=True)
-    assert e_phi <= 1e-12 and e_f <= 1e-12
-    assert np.max(np.abs(phi)) == pytest.approx(max_phi, rel=1e-12)
-    assert np.sum(np.abs(phi)) == pytest.approx(float(ref["sum_abs_phi"]), rel=1e-12)
-    assert np.sum(phi * phi) == pytest.approx(float(ref["sum_phi_sq"]), rel=1e-12)
-    assert abs(np.sum(phi) - float(ref["sum_phi"])) <= 1e-12 * float(ref["sum_abs_phi"])
+    eps = 1e-12
+    assert e_phi <= eps and e_f <= eps
+    n = w.nx * w.ny
+    d = eps * max_phi
+    sum_abs = float(ref["sum_abs_phi"])
+    assert abs(np.max(np.abs(phi)) - max_phi) <= d
+    assert abs(np.sum(np.abs(phi)) - sum_abs) <= n * d
+    assert abs(np.sum(phi) - float(ref["sum_phi"])) <= n * d
+    assert abs(np.sum(phi * phi) - float(ref["sum_phi_sq"])) <= 2 * d * sum_abs + n * d * d
