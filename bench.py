@@ -42,22 +42,31 @@ def sweep_launches(steps, fusion):
     done = 0
     while done < steps:
         k = min(CHECK_INTERVAL, steps - done)
-        n += k // fusion + k % fusion
+        n += k // fusion + (1 if k % fusion else 0)
         done += k
     return n
 
 
-def timed_run(w, precision, steps, warmup, fusion=2):
-    """Warm up, then time exactly ``steps`` steps with HIP events on the library's stream."""
+def timed_run(w, precision, steps, warmup, fusion=0):
+    """Warm up, then time exactly ``steps`` steps with HIP events on the library's stream.
+
+    fusion 0: the warm-up starts with btrt_tune (real steps on the live state, at most 300)
+    and the fastest launch shape is kept; 1..4: that many steps per launch, automatic strips."""
     import torch
     from paper_1902_09813_amd import btrt
 
     prob = btrt.problem_from_workload(w, precision=precision, check_interval=CHECK_INTERVAL)
     solver = btrt.Solver(prob, w.phi0(), torch_memory=True)  # torch memory + a torch stream
-    solver.set_fusion(fusion)
     stream = solver.torch_stream  # the stream every kernel of the solver is launched on
     info = solver.info()
-    solver.step(warmup)
+    tuned = 0
+    if fusion:
+        solver.set_fusion(fusion)
+    else:
+        _, tuned = solver.tune(300)
+    shape = solver.launch()
+    fusion = shape[0]
+    solver.step(max(0, warmup - tuned))
     solver.sync()
     torch.cuda.synchronize()
 
@@ -98,6 +107,8 @@ def timed_run(w, precision, steps, warmup, fusion=2):
         "bytes_per_node_launch": info.bytes_per_node_launch,
         "nodes": nodes,
         "residual": residual,
+        "launch": {"steps_per_launch": shape[0], "strip_rows": shape[1], "strips_per_group": shape[2],
+                   "tile": shape[3]},
     }
 
 
@@ -228,9 +239,14 @@ def cpu_baseline(w, budget_s=15.0):
     }
 
 
-def traffic_for(precision_name, nodes, fusion):
+def traffic_key(precision_name, launch):
+    return (f"{precision_name}_k{launch['steps_per_launch']}_r{launch['strip_rows']}"
+            f"_g{launch['strips_per_group']}_t{launch['tile']}")
+
+
+def traffic_for(precision_name, nodes, launch):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None if the
-    kernel source changed since the counters were taken."""
+    kernel source changed since the counters were taken or that shape was not measured."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -238,7 +254,7 @@ def traffic_for(precision_name, nodes, fusion):
         return None
     if rec.get("kernel_sha256_16") != kernel_hash():
         return None
-    ent = rec.get(f"{precision_name}_fusion{fusion}")
+    ent = rec.get(traffic_key(precision_name, launch))
     if not ent or ent.get("nodes") != nodes:
         return None
     return ent.get("bytes_per_launch")
@@ -262,7 +278,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", choices=["f64", "f32", "f16dev", "bf16dev"], default="f64")
-    ap.add_argument("--fusion", type=int, choices=[1, 2], default=2, help="time steps per sweep launch")
+    ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4], default=0,
+                    help="time steps per sweep launch (0: tuned during the warm-up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
@@ -298,14 +315,15 @@ def main():
     achieved = bytes_per_launch / (r["launch_ms_avg"] * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": "sweep2_kernel" if args.fusion == 2 else "sweep_kernel",
+        "kernel": ("sweep_kernel" if r["launch"]["steps_per_launch"] == 1 else
+                   "sweep2_kernel" if r["launch"]["tile"] else "walk_kernel"),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(args.precision, r["nodes"], args.fusion),
+        "traffic": traffic_for(args.precision, r["nodes"], r["launch"]),
         "bytes_per_launch": bytes_per_launch,
-        "steps_per_launch": args.fusion,
+        "launch": r["launch"],
         "launch_us_avg": round(r["launch_ms_avg"] * 1e3, 2),
     }
     extra = {}
@@ -318,10 +336,13 @@ def main():
             extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
             extra[f"c3_{name}_hbm_frac"] = round(
                 r2["bytes_per_node_launch"] * r2["nodes"] / (r2["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        r1 = timed_run(w, prec, min(args.steps, 1000), 20, 1)
-        extra[f"c3_{args.precision}_one_step_per_launch_mlups"] = round(r1["mlups"], 1)
-        extra[f"c3_{args.precision}_one_step_per_launch_hbm_frac"] = round(
-            r1["bytes_per_node_launch"] * r1["nodes"] / (r1["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        for k in (1, 2, 3, 4):
+            print(f"[bench] side measurement: {w.name} {args.precision}, {k} steps per launch", file=sys.stderr,
+                  flush=True)
+            rk = timed_run(w, prec, min(args.steps, 1000), 20, k)
+            extra[f"c3_{args.precision}_fusion{k}_mlups"] = round(rk["mlups"], 1)
+            extra[f"c3_{args.precision}_fusion{k}_hbm_frac"] = round(
+                rk["bytes_per_node_launch"] * rk["nodes"] / (rk["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         w2 = W.c2()
         print(f"[bench] side measurement: {w2.name} f64", file=sys.stderr, flush=True)
         r3 = timed_run(w2, btrt.F64, 2000, 50, args.fusion)

@@ -163,10 +163,42 @@ int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t
  * returns without waiting. */
 int btrt_step(btrt_t* h, int64_t n);
 
-/* Time steps fused into one kernel launch by btrt_step: 2 (the default) runs two steps per
- * launch through an on-chip tile, halving HBM traffic per step; 1 runs one step per launch.
- * Both give bitwise identical results. Errors: BTRT_E_INVAL for other values. */
+/* Shape of the sweep launches btrt_step makes. Every shape gives bitwise identical results;
+ * only the speed differs. Zero fields are chosen by the library for the grid.
+ *   steps_per_launch  1 .. 4 time steps per launch (0: 4 from 2^20 nodes up, else 1). With
+ *                     k >= 2 each wavefront walks a strip of 66 - 2k columns down the grid and
+ *                     keeps the k - 1 intermediate time levels in registers, so the state is
+ *                     read and written once per k steps. Step counts that are not a multiple of
+ *                     k end with one shorter launch.
+ *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size)
+ *   strips_per_group  1 or 4 strips per workgroup, walked side by side in lockstep (0: auto)
+ *   tile              1 with steps_per_launch 2: the two-step LDS tile kernel instead of a
+ *                     strip walker (tiles of 64 x 8 nodes in FP64, 64 x 16 otherwise) */
+typedef struct {
+    int32_t steps_per_launch;
+    int32_t strip_rows;
+    int32_t strips_per_group;
+    int32_t tile;
+} btrt_launch_t;
+
+/* Sets the launch shape; fields as above. Errors: BTRT_E_INVAL (steps outside [0, 4],
+ * strip_rows < 0, strips_per_group not 0, 1 or 4, tile without steps_per_launch 2). */
+int btrt_set_launch(btrt_t* h, const btrt_launch_t* cfg);
+
+/* The launch shape in force, with the automatic fields resolved for this grid. */
+int btrt_get_launch(btrt_t* h, btrt_launch_t* cfg);
+
+/* Shorthand for btrt_set_launch({steps_per_launch, 0, 0, 0}); steps_per_launch in [1, 4]
+ * (BTRT_E_INVAL otherwise). */
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch);
+
+/* Times candidate launch shapes on the handle's own state and keeps the fastest (per step):
+ * one step per launch, the LDS tile, and strip walkers over 2 .. 4 steps x 8, 16, 32, 64, 128 rows
+ * x 1, 4 strips per group, each for one untimed and two timed launches, as far as max_steps
+ * allows. The state advances by *steps_used steps (the same bits btrt_step would give);
+ * the Eq. (64) snapshot is not touched. Synchronises. best (may be NULL) receives the shape
+ * kept, resolved. */
+int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_used);
 
 /* phi(t) = sum_i f_i(x, t) (Eq. (9)) into phi_out[nx*ny]. Synchronises. */
 int btrt_field(btrt_t* h, double* phi_out);

@@ -24,7 +24,8 @@ D_PHI_I = 0
 K2_VALUE, K2_HBB = 0, 1
 
 # Every function include/btrt.h declares.
-EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_fusion", "btrt_field",
+EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_launch", "btrt_get_launch",
+           "btrt_set_fusion", "btrt_tune", "btrt_field",
            "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
            "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error",
            "btrt_batch_create", "btrt_batch_step", "btrt_batch_field", "btrt_batch_residual",
@@ -77,6 +78,14 @@ class Info(ctypes.Structure):
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("grid", Grid), ("B", Flux), ("K", Diff), ("D", DTerm), ("R", Source), ("bc", BC),
                 ("relax", Relax), ("phi0", ctypes.POINTER(ctypes.c_double))]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int32), ("strip_rows", ctypes.c_int32),
+                ("strips_per_group", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.steps_per_launch, self.strip_rows, self.strips_per_group, self.tile)
 
 
 class BatchConfig(ctypes.Structure):
@@ -147,6 +156,9 @@ def lib() -> ctypes.CDLL:
             "btrt_create": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, P(hp)], ctypes.c_int),
             "btrt_step": ([hp, ctypes.c_int64], ctypes.c_int),
             "btrt_set_fusion": ([hp, ctypes.c_int32], ctypes.c_int),
+            "btrt_set_launch": ([hp, P(Launch)], ctypes.c_int),
+            "btrt_get_launch": ([hp, P(Launch)], ctypes.c_int),
+            "btrt_tune": ([hp, ctypes.c_int64, P(Launch), P(ctypes.c_int64)], ctypes.c_int),
             "btrt_field": ([hp, dp], ctypes.c_int),
             "btrt_populations": ([hp, dp], ctypes.c_int),
             "btrt_residual": ([hp, dp], ctypes.c_int),
@@ -284,6 +296,26 @@ class Solver:
     def set_fusion(self, steps_per_launch: int) -> "Solver":
         _check(lib().btrt_set_fusion(self.h, int(steps_per_launch)), "btrt_set_fusion")
         return self
+
+    def set_launch(self, steps_per_launch: int = 0, strip_rows: int = 0, strips_per_group: int = 0,
+                   tile: int = 0) -> "Solver":
+        cfg = Launch(int(steps_per_launch), int(strip_rows), int(strips_per_group), int(tile))
+        _check(lib().btrt_set_launch(self.h, ctypes.byref(cfg)), "btrt_set_launch")
+        return self
+
+    def launch(self) -> tuple:
+        """(steps_per_launch, strip_rows, strips_per_group, tile) in force, resolved."""
+        cfg = Launch()
+        _check(lib().btrt_get_launch(self.h, ctypes.byref(cfg)), "btrt_get_launch")
+        return cfg.as_tuple()
+
+    def tune(self, max_steps: int):
+        """Times launch shapes on the live state (advancing it) and keeps the fastest; returns
+        (shape tuple, steps used)."""
+        cfg = Launch()
+        used = ctypes.c_int64()
+        _check(lib().btrt_tune(self.h, int(max_steps), ctypes.byref(cfg), ctypes.byref(used)), "btrt_tune")
+        return cfg.as_tuple(), int(used.value)
 
     def field(self) -> np.ndarray:
         out = np.empty((self.problem.ny, self.problem.nx), dtype=np.float64)

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
 using namespace btrth;
 using btrtk::kError;
@@ -22,22 +23,44 @@ struct btrt {
     char* mem = nullptr;
     bool own_mem = false;
     int check_interval = 1000;
-    int fuse = 2;  // time steps fused per sweep launch (1 or 2)
+    btrtk::LaunchCfg launch{};  // requested launch shape (zero fields: automatic)
     Instance inst;
 };
 
 namespace {
 
-int enqueue_steps(btrt* h, int64_t n)
+using btrtk::LaunchCfg;
+
+// n steps as launches of the handle's shape; a count that is not a multiple of its steps per
+// launch ends with one shorter launch.
+int enqueue_steps(btrt* h, const LaunchCfg& want, int64_t n)
 {
+    if (n <= 0) return BTRT_OK;
+    const LaunchCfg c = instance_resolve(h->inst, want);
     for (int64_t i = 0; i < n;) {
-        const int k = (h->fuse >= 2 && n - i >= 2) ? 2 : 1;
+        LaunchCfg k = c;
+        k.steps = static_cast<int>(std::min<int64_t>(c.steps, n - i));
+        if (k.steps != 2) k.tile = 0;
         int rc = instance_launch(h->inst, k, h->stream);
         if (rc != BTRT_OK) return rc;
-        i += k;
+        i += k.steps;
     }
     return BTRT_OK;
 }
+
+int enqueue_steps(btrt* h, int64_t n) { return enqueue_steps(h, h->launch, n); }
+
+bool launch_ok(const btrt_launch_t* c)
+{
+    return c && c->steps_per_launch >= 0 && c->steps_per_launch <= btrtk::kMaxFuse && c->strip_rows >= 0 &&
+           c->strip_rows <= (1 << 24) &&
+           (c->strips_per_group == 0 || c->strips_per_group == 1 || c->strips_per_group == btrtk::kWalkGroup) &&
+           (c->tile == 0 || (c->tile == 1 && c->steps_per_launch == 2));
+}
+
+LaunchCfg to_cfg(const btrt_launch_t& c) { return LaunchCfg{c.steps_per_launch, c.strip_rows, c.strips_per_group, c.tile}; }
+
+btrt_launch_t to_public(const LaunchCfg& c) { return btrt_launch_t{c.steps, c.rows, c.group, c.tile}; }
 
 int reduce_sync(btrt* h, int mode, double out[kReducePartials])
 {
@@ -154,9 +177,84 @@ int btrt_step(btrt_t* h, int64_t n)
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch)
 {
     if (!h) return fail(BTRT_E_STATE, "NULL handle");
-    if (steps_per_launch != 1 && steps_per_launch != 2)
-        return fail(BTRT_E_INVAL, "steps_per_launch = %d: must be 1 or 2", steps_per_launch);
-    h->fuse = steps_per_launch;
+    if (steps_per_launch < 1 || steps_per_launch > btrtk::kMaxFuse)
+        return fail(BTRT_E_INVAL, "steps_per_launch = %d: must be in [1, %d]", steps_per_launch, btrtk::kMaxFuse);
+    h->launch = LaunchCfg{steps_per_launch, 0, 0, 0};
+    return ok();
+}
+
+int btrt_set_launch(btrt_t* h, const btrt_launch_t* cfg)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (!launch_ok(cfg)) return fail(BTRT_E_INVAL, "invalid launch configuration");
+    h->launch = to_cfg(*cfg);
+    return ok();
+}
+
+int btrt_get_launch(btrt_t* h, btrt_launch_t* cfg)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (!cfg) return fail(BTRT_E_INVAL, "cfg is NULL");
+    DeviceGuard g(h->device);
+    *cfg = to_public(instance_resolve(h->inst, h->launch));
+    return ok();
+}
+
+int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_used)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (max_steps < 0) return fail(BTRT_E_INVAL, "max_steps < 0");
+    DeviceGuard g(h->device);
+    // Candidates: one step per launch, the two-step LDS tile, and strip walkers over steps per
+    // launch x strip rows x strips per group. Each runs one untimed launch and kReps timed ones.
+    std::vector<LaunchCfg> cand{{1, 0, 0, 0}, {2, 0, 0, 1}};
+    for (int k = 2; k <= btrtk::kMaxFuse; ++k)
+        for (int rows : {8, 16, 32, 64, 128})
+            for (int grp : {1, btrtk::kWalkGroup}) cand.push_back(LaunchCfg{k, rows, grp, 0});
+    constexpr int kReps = 2;
+    std::vector<hipEvent_t> ev;
+    std::vector<size_t> timed;
+    int64_t used = 0;
+    int rc = BTRT_OK;
+    for (size_t c = 0; c < cand.size() && rc == BTRT_OK; ++c) {
+        const int64_t need = static_cast<int64_t>(1 + kReps) * cand[c].steps;
+        if (used + need > max_steps) continue;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            rc = fail(BTRT_E_DEVICE, "hipEventCreate failed");
+            break;
+        }
+        ev.push_back(e0);
+        ev.push_back(e1);
+        rc = enqueue_steps(h, cand[c], cand[c].steps);
+        if (rc == BTRT_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
+        if (rc == BTRT_OK) rc = enqueue_steps(h, cand[c], static_cast<int64_t>(kReps) * cand[c].steps);
+        if (rc == BTRT_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
+        used += need;
+        timed.push_back(c);
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (rc == BTRT_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    double best_ms = -1.0;
+    LaunchCfg pick = h->launch;
+    for (size_t j = 0; j < timed.size() && rc == BTRT_OK; ++j) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]) != hipSuccess) {
+            rc = fail(BTRT_E_DEVICE, "hipEventElapsedTime failed");
+            break;
+        }
+        const double per_step = ms / (kReps * cand[timed[j]].steps);
+        if (best_ms < 0 || per_step < best_ms) {
+            best_ms = per_step;
+            pick = cand[timed[j]];
+        }
+    }
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    if (rc != BTRT_OK) return rc;
+    h->launch = pick;
+    if (best) *best = to_public(instance_resolve(h->inst, pick));
+    if (steps_used) *steps_used = used;
     return ok();
 }
 

@@ -385,18 +385,24 @@ template SweepArgs<float> sweep_args<float>(const Instance&, int);
 template GatherArgs<double> gather_args<double>(const Instance&);
 template GatherArgs<float> gather_args<float>(const Instance&);
 
-int instance_launch(Instance& I, int steps, hipStream_t s)
+int instance_launch(Instance& I, const LaunchCfg& cfg, hipStream_t s)
 {
     hipError_t e;
     if (I.precision == BTRT_F64)
-        e = launch_sweep<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, steps, s);
+        e = launch_sweep<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, cfg, s);
     else
-        e = launch_sweep<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, steps,
-                                s);
+        e = launch_sweep<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, cfg, s);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     I.cur ^= 1;
-    I.step += steps;
+    I.step += cfg.steps;
     return BTRT_OK;
+}
+
+LaunchCfg instance_resolve(const Instance& I, const LaunchCfg& cfg)
+{
+    if (I.precision == BTRT_F64)
+        return resolve_launch<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, cfg);
+    return resolve_launch<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, cfg);
 }
 
 int instance_reduce_async(Instance& I, int mode, hipStream_t s)

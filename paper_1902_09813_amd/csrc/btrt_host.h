@@ -88,8 +88,11 @@ SweepArgs<T> sweep_args(const Instance& I, int parity);
 template <typename T>
 GatherArgs<T> gather_args(const Instance& I);
 
-// One sweep launch advancing `steps` (1 or 2) time steps; flips the parity.
-int instance_launch(Instance& I, int steps, hipStream_t s);
+// One sweep launch of shape cfg (cfg.steps >= 1 time steps; automatic fields allowed); flips
+// the parity.
+int instance_launch(Instance& I, const btrtk::LaunchCfg& cfg, hipStream_t s);
+// cfg with its automatic fields resolved for I's grid and format on the current device.
+btrtk::LaunchCfg instance_resolve(const Instance& I, const btrtk::LaunchCfg& cfg);
 // Enqueues the two-pass reduction (residual or error) into I's result slot (no sync).
 int instance_reduce_async(Instance& I, int mode, hipStream_t s);
 // Copies I's result slot to out (async).

@@ -35,6 +35,7 @@ struct SweepArgs {
     T src_amp;
     T dev_scale, dev_inv; // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq)), f+ = f_eq + h dev_inv
     int tiles_x, tiles_y; // set by the launcher for the kernel it picks
+    int rows;             // rows per strip of the strip walkers (set by the launcher)
     int nts;              // 1: non-temporal stores (grids much larger than the caches)
 };
 
@@ -63,15 +64,31 @@ struct BatchEntry {
     int pad;
 };
 
+constexpr int kMaxFuse = 4;         // most time steps one sweep launch can fuse
 constexpr int kReducePartials = 6; // sum a, sum b, sum c, sum d, max, non-finite count
 constexpr int kReduceBlocks = 1024;
 constexpr int kBlock = 256;
 
+// Shape of one sweep launch; every shape gives bitwise identical results.
+struct LaunchCfg {
+    int steps = 0;  // time steps per launch, 1 .. kMaxFuse (0: automatic)
+    int rows = 0;   // strip walkers (steps >= 2): rows per strip (0: automatic)
+    int group = 0;  // strip walkers: strips per workgroup, 1 or kWalkGroup (0: automatic)
+    int tile = 0;   // 1: steps == 2 through the LDS tile kernel instead of a strip walker
+};
+constexpr int kWalkGroup = 4;
+
 // Launchers (defined in btrt_kernels.hip). They return the launch's hipError_t. fmt selects
-// the storage format (kFmtPlain for double; any for float).
-// steps: 1 (one time step) or 2 (two fused time steps through LDS).
+// the storage format (kFmtPlain for double; any for float). cfg.steps (1 .. kMaxFuse) time
+// steps advance in the launch: one node per thread for 1, strip walkers (intermediate time
+// levels in registers) or the LDS tile kernel for more; automatic fields of cfg are resolved
+// as resolve_launch does.
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, int steps, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+                        hipStream_t s);
+// cfg with its automatic fields filled in for this grid, format and device (the current one).
+template <typename T>
+LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, LaunchCfg cfg);
 // f+(-1) and phi(-1) := phi0 into a.fin / a.phi_prev (see init_values); FP64 arithmetic.
 template <typename T>
 hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,

@@ -68,12 +68,23 @@ __device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int 
 template <typename T_>
 struct Plain {
     using T = T_;
-    __device__ static void pull(const SweepArgs<T>& a, int x, int y, T f[9])
+    __device__ __forceinline__ static void pull(const SweepArgs<T>& a, int x, int y, T f[9])
     {
         gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
     }
-    __device__ static void settle(const SweepArgs<T>&, T*, T) {}
-    __device__ static void put(const SweepArgs<T>& a, int n, const T f[9], T phi)
+    __device__ __forceinline__ static void settle(const SweepArgs<T>&, T*, T) {}
+    // Raw loads of one node's pull (see walk_load): value read for each direction.
+    struct Raw {
+        T v[9];
+    };
+    __device__ __forceinline__ static void fetch(const SweepArgs<T>& a, const int plane[9], const int idx[9], Raw& r)
+    {
+        const int64_t p = a.plane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r.v[i] = a.fin[plane[i] * p + idx[i]];
+    }
+    __device__ __forceinline__ static T value(const SweepArgs<T>&, const Raw& r, int i, int, bool) { return r.v[i]; }
+    __device__ __forceinline__ static void put(const SweepArgs<T>& a, int n, const T f[9], T phi)
     {
         const int64_t p = a.plane;
 #pragma unroll
@@ -84,34 +95,34 @@ struct Plain {
 
 // IEEE binary16, round to nearest even.
 struct F16Codec {
-    __device__ static unsigned short enc(float v) { return __builtin_bit_cast(unsigned short, static_cast<_Float16>(v)); }
-    __device__ static float dec(unsigned short h) { return static_cast<float>(__builtin_bit_cast(_Float16, h)); }
+    __device__ __forceinline__ static unsigned short enc(float v) { return __builtin_bit_cast(unsigned short, static_cast<_Float16>(v)); }
+    __device__ __forceinline__ static float dec(unsigned short h) { return static_cast<float>(__builtin_bit_cast(_Float16, h)); }
 };
 
 // bfloat16 (the upper half of an FP32), round to nearest even.
 struct BF16Codec {
-    __device__ static unsigned short enc(float v)
+    __device__ __forceinline__ static unsigned short enc(float v)
     {
         unsigned u = __builtin_bit_cast(unsigned, v);
         if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);  // NaN stays NaN
         u += 0x7fffu + ((u >> 16) & 1u);
         return static_cast<unsigned short>(u >> 16);
     }
-    __device__ static float dec(unsigned short h) { return __builtin_bit_cast(float, static_cast<unsigned>(h) << 16); }
+    __device__ __forceinline__ static float dec(unsigned short h) { return __builtin_bit_cast(float, static_cast<unsigned>(h) << 16); }
 };
 
 template <typename C>
 struct Dev {
     using T = float;
-    __device__ static float rebuild(const SweepArgs<float>& a, int i, float phi, unsigned short h)
+    __device__ __forceinline__ static float rebuild(const SweepArgs<float>& a, int i, float phi, unsigned short h)
     {
         return fmadd(C::dec(h), a.dev_inv, feq_dir(i, phi, a.ax, a.ay, a.bx, a.by));
     }
-    __device__ static unsigned short quant(const SweepArgs<float>& a, int i, float f, float phi)
+    __device__ __forceinline__ static unsigned short quant(const SweepArgs<float>& a, int i, float f, float phi)
     {
         return C::enc((f - feq_dir(i, phi, a.ax, a.ay, a.bx, a.by)) * a.dev_scale);
     }
-    __device__ static void pull(const SweepArgs<float>& a, int x, int y, float f[9])
+    __device__ __forceinline__ static void pull(const SweepArgs<float>& a, int x, int y, float f[9])
     {
         const unsigned short* __restrict__ H = reinterpret_cast<const unsigned short*>(a.fin);
         const float* __restrict__ P = a.phi_prev;
@@ -119,12 +130,35 @@ struct Dev {
         gather_with<float>([&](int i, int idx) { return rebuild(a, i, P[idx], H[i * p + idx]); }, x, y, a.nx, a.ny,
                            a.pitch, a.perx, a.pery, a.wall, f);
     }
-    __device__ static void settle(const SweepArgs<float>& a, float f[9], float phi)
+    // Raw loads of one node's pull: the 16-bit code and phi(t-1) of the node it comes from.
+    struct Raw {
+        unsigned short h[9];
+        float p[9];
+    };
+    __device__ __forceinline__ static void fetch(const SweepArgs<float>& a, const int plane[9], const int idx[9],
+                                                 Raw& r)
+    {
+        const unsigned short* __restrict__ H = reinterpret_cast<const unsigned short*>(a.fin);
+        const int64_t p = a.plane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            r.h[i] = H[plane[i] * p + idx[i]];
+            r.p[i] = a.phi_prev[idx[i]];
+        }
+    }
+    // Value read for direction i: population i of the source node, or, when `own`
+    // (bounce-back), population o (the opposite direction) of the node itself.
+    __device__ __forceinline__ static float value(const SweepArgs<float>& a, const Raw& r, int i, int o, bool own)
+    {
+        const float e = own ? feq_dir(o, r.p[i], a.ax, a.ay, a.bx, a.by) : feq_dir(i, r.p[i], a.ax, a.ay, a.bx, a.by);
+        return fmadd(C::dec(r.h[i]), a.dev_inv, e);
+    }
+    __device__ __forceinline__ static void settle(const SweepArgs<float>& a, float f[9], float phi)
     {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = rebuild(a, i, phi, quant(a, i, f[i], phi));
     }
-    __device__ static void put(const SweepArgs<float>& a, int n, const float f[9], float phi)
+    __device__ __forceinline__ static void put(const SweepArgs<float>& a, int n, const float f[9], float phi)
     {
         unsigned short* __restrict__ H = reinterpret_cast<unsigned short*>(a.fout);
         const int64_t p = a.plane;
@@ -166,7 +200,7 @@ __device__ __forceinline__ int wrap(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// ---- two time steps per launch --------------------------------------------------------------
+// ---- two time steps per tile through LDS -------------------------------------------------------
 // Step 1 runs on a kTile2X x TY tile plus a one-node ring, pulling f+(t-1) from global memory,
 // and leaves f+(t) (as the next pull would see it) and phi(t) in LDS; step 2 runs on the tile,
 // pulling f+(t) from LDS (bounce-back at Dirichlet walls uses the node's own LDS values), and
@@ -269,6 +303,283 @@ __global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<typename F::T
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
     tile2<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, lf, lphi);
+}
+
+// ---- K time steps per launch: strip walkers ------------------------------------------------
+// One wavefront owns a strip of W = 64 - 2(K-1) columns by a.rows rows and walks down it one row
+// per iteration; its 64 lanes hold the strip plus K-1 halo columns on each side. In iteration r,
+// step 1 of the launch updates row r from the populations in global memory, and step l
+// (l = 2..K) updates row r-(l-1) from rows r-l .. r-l+2 of step l-1, which stay in registers
+// (the row below, the row itself and the row step l-1 has just produced); the x-1 / x+1
+// neighbours come from the adjacent lanes through DPP wavefront shifts. Step K stores. Each
+// step narrows the valid region by one node per side, so step l is valid on lanes l-1 .. 64-l
+// and rows ys-(K-l) .. ys+L-1+(K-l). There is no LDS and no barrier; the state is read and
+// written once per launch, plus the halo columns (64/W) and rows ((L+2(K-1))/L) on the read side.
+// Every node update is the same arithmetic as in sweep_kernel (collide and the format's round
+// trip), so K steps in one launch give the bits of K single steps.
+
+constexpr int kWave = 64;
+constexpr int kShr1 = 0x138;  // DPP wave_shr:1, lane j receives lane j-1
+constexpr int kShl1 = 0x130;  // DPP wave_shl:1, lane j receives lane j+1
+
+template <int CTRL>
+__device__ __forceinline__ int lane_shift_b32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v)
+{
+    return __builtin_bit_cast(float, lane_shift_b32<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(lane_shift_b32<CTRL>(static_cast<int>(static_cast<unsigned>(u))));
+    const unsigned hi = static_cast<unsigned>(lane_shift_b32<CTRL>(static_cast<int>(static_cast<unsigned>(u >> 32))));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+template <int K>
+struct Walk {
+    static constexpr int W = kWave - 2 * (K - 1);  // output columns per strip
+};
+
+// One row of one time level as the next level pulls it: f+ (after the format's round trip)
+// and phi.
+template <typename T>
+struct Level {
+    T f[9];
+    T phi;
+};
+
+// What level l+1 keeps of level l between iterations: the populations of the row below the
+// one it updates next that move up (2, 5, 6), and that row itself.
+template <typename T>
+struct Carry {
+    T up2, up5, up6;
+    Level<T> mid;
+};
+
+// Row coordinate of a walker: wrapped into the grid (periodic), with validity and wall flags.
+struct WalkRow {
+    int y;       // row inside [0, ny) (clamped when invalid)
+    bool ok;     // a node row of the grid
+    bool okm;    // the y-1 pull is a node (else bounce-back at the y- wall)
+    bool okp;    // the y+1 pull is a node (else bounce-back at the y+ wall)
+};
+
+__device__ __forceinline__ WalkRow walk_row(int q, int ny, int pery)
+{
+    WalkRow w;
+    if (pery) {
+        w.y = wrap(q, ny);
+        w.ok = true;
+        w.okm = w.okp = true;
+    } else {
+        w.ok = q >= 0 && q < ny;
+        w.y = q < 0 ? 0 : (q >= ny ? ny - 1 : q);
+        w.okm = w.y > 0;
+        w.okp = w.y < ny - 1;
+    }
+    return w;
+}
+
+// Level l >= 2 at one node: pull from the carried rows of level l-1 and the row it has just
+// produced (`fresh`), collide; the carry advances by one row. All lanes must be active here
+// (the wavefront shifts read the neighbouring lanes).
+template <typename T, int SRC, bool KPHI>
+__device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, Carry<T>& c, const Level<T>& fresh, int x, bool okxm,
+                                          bool okxp, const WalkRow& row, T g[9])
+{
+    const T s1 = lane_shift<kShr1>(c.mid.f[1]);
+    const T s3 = lane_shift<kShl1>(c.mid.f[3]);
+    const T s5 = lane_shift<kShr1>(c.up5);
+    const T s6 = lane_shift<kShl1>(c.up6);
+    const T s7 = lane_shift<kShl1>(fresh.f[7]);
+    const T s8 = lane_shift<kShr1>(fresh.f[8]);
+    const T* m = c.mid.f;
+    const bool okym = row.okm, okyp = row.okp;
+    const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
+    g[0] = m[0];
+    g[1] = okxm ? s1 : bounce(m[3], tw1, a.wall[0]);
+    g[2] = okym ? c.up2 : bounce(m[4], tw1, a.wall[2]);
+    g[3] = okxp ? s3 : bounce(m[1], tw1, a.wall[1]);
+    g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, a.wall[3]);
+    g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
+    g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
+    g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
+    g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+    const T phi_prev = c.mid.phi;
+    c.up2 = m[2];
+    c.up5 = m[5];
+    c.up6 = m[6];
+    c.mid = fresh;
+    const int n = row.y * a.pitch + x;
+    return collide<T, SRC, KPHI>(a, g, phi_prev, source_at<T, SRC>(a, n, x, row.y));
+}
+
+// Level-1 inputs of row r at column x, as raw loads: for each direction the source address is
+// the neighbour x - c_i (wrapped on periodic sides) or, when that lies beyond a Dirichlet wall,
+// the node's own opposite population (bounce-back); every load is issued unconditionally from a
+// valid address and the values are only used (bounce-back, decoding) an iteration later.
+template <typename F>
+struct WalkIn {
+    typename F::Raw raw;
+    typename F::T phi;  // phi(t-1) of the node
+    int ok;             // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
+};
+
+template <typename F>
+__device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int x, bool colok, int r, WalkIn<F>& in)
+{
+    const WalkRow w = walk_row(r, a.ny, a.pery);
+    const int nx = a.nx, ny = a.ny, pitch = a.pitch, y = w.y;
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool okxm = true, okxp = true, okym = true, okyp = true;
+    if (xm < 0) { if (a.perx) xm += nx; else { okxm = false; xm = x; } }
+    if (xp >= nx) { if (a.perx) xp -= nx; else { okxp = false; xp = x; } }
+    if (ym < 0) { if (a.pery) ym += ny; else { okym = false; ym = y; } }
+    if (yp >= ny) { if (a.pery) yp -= ny; else { okyp = false; yp = y; } }
+    const int n = y * pitch + x, r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
+    const bool ok5 = okxm && okym, ok6 = okxp && okym, ok7 = okxp && okyp, ok8 = okxm && okyp;
+    const int plane[9] = {0, okxm ? 1 : 3, okym ? 2 : 4, okxp ? 3 : 1, okyp ? 4 : 2,
+                          ok5 ? 5 : 7, ok6 ? 6 : 8, ok7 ? 7 : 5, ok8 ? 8 : 6};
+    const int idx[9] = {n, okxm ? r0 + xm : n, okym ? rm + x : n, okxp ? r0 + xp : n, okyp ? rp + x : n,
+                        ok5 ? rm + xm : n, ok6 ? rm + xp : n, ok7 ? rp + xp : n, ok8 ? rp + xm : n};
+    F::fetch(a, plane, idx, in.raw);
+    in.phi = a.phi_prev[n];
+    in.ok = (okxm ? 1 : 0) | (okxp ? 2 : 0) | (okym ? 4 : 0) | (okyp ? 8 : 0) | ((colok && w.ok) ? 16 : 0);
+}
+
+// f(x, t) from the raw loads (bounce-back at Dirichlet walls, Eqs. (54)-(56)); zeros where the
+// lane is not a node.
+template <typename F>
+__device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, const WalkIn<F>& in,
+                                            typename F::T f[9], typename F::T& phi_prev)
+{
+    using T = typename F::T;
+    const bool okxm = in.ok & 1, okxp = in.ok & 2, okym = in.ok & 4, okyp = in.ok & 8, node = in.ok & 16;
+    const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
+    const bool ok[9] = {true, okxm, okym, okxp, okyp, okxm && okym, okxp && okym, okxp && okyp, okxm && okyp};
+    constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    T v[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = F::value(a, in.raw, i, opp[i], !ok[i]);
+    f[0] = v[0];
+    f[1] = ok[1] ? v[1] : bounce(v[1], tw1, a.wall[0]);
+    f[2] = ok[2] ? v[2] : bounce(v[2], tw1, a.wall[2]);
+    f[3] = ok[3] ? v[3] : bounce(v[3], tw1, a.wall[1]);
+    f[4] = ok[4] ? v[4] : bounce(v[4], tw1, a.wall[3]);
+    f[5] = ok[5] ? v[5] : bounce(v[5], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
+    f[6] = ok[6] ? v[6] : bounce(v[6], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
+    f[7] = ok[7] ? v[7] : bounce(v[7], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
+    f[8] = ok[8] ? v[8] : bounce(v[8], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+    phi_prev = in.phi;
+    if (!node) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = T(0);
+        phi_prev = T(0);
+    }
+}
+
+// A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
+// in one band of rows; they walk in lockstep (one barrier per row, no memory fence: they share
+// no data), so the rows they read and write at a time are contiguous across the group.
+template <typename F, int SRC, bool KPHI, int K>
+__global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typename F::T> a)
+{
+    using T = typename F::T;
+    constexpr int W = Walk<K>::W;
+    const int gsize = static_cast<int>(blockDim.x) / kWave;
+    const int group = xcd_tile();
+    const int groups_x = (a.tiles_x + gsize - 1) / gsize;
+    const int sy = group / groups_x;
+    const int sx = (group - sy * groups_x) * gsize + static_cast<int>(threadIdx.x / kWave);
+    const bool live = sx < a.tiles_x;  // the last group of a band may have fewer strips
+    const int lane = static_cast<int>(threadIdx.x % kWave);
+    const int nx = a.nx, ny = a.ny;
+
+    // Column of this lane (K-1 halo columns on each side of the strip).
+    const int xs = sx * W;
+    const int cx = xs - (K - 1) + lane;
+    int x;
+    bool colok;
+    if (a.perx) {
+        x = wrap(cx, nx);
+        colok = live;
+    } else {
+        colok = live && cx >= 0 && cx < nx;
+        x = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx);
+    }
+    const bool okxm = a.perx || x > 0, okxp = a.perx || x < nx - 1;
+    const bool store_col = live && lane >= K - 1 && lane < kWave - (K - 1) && cx < nx;
+
+    const int ys = sy * a.rows;
+    const int ye = min(ys + a.rows, ny);  // output rows ys .. ye-1 (uniform over the group)
+    const int r0 = ys - (K - 1), r1 = ye + (K - 1);
+
+    Carry<T> carry[K - 1];
+#pragma unroll
+    for (int l = 0; l < K - 1; ++l) {
+        carry[l].up2 = carry[l].up5 = carry[l].up6 = T(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) carry[l].mid.f[i] = T(0);
+        carry[l].mid.phi = T(0);
+    }
+
+    // Level-1 loads run one row ahead. The last level's row is stored one iteration late, after
+    // level 1 has consumed the loads and just before the next loads are issued, so every wait
+    // covers memory operations issued a full iteration earlier.
+    WalkIn<F> in;
+    walk_load<F>(a, x, colok, r0, in);
+    Level<T> out;
+    int out_n = -1;
+    for (int r = r0; r < r1; ++r) {
+        __builtin_amdgcn_s_barrier();
+        Level<T> lev;
+        walk_finish<F>(a, in, lev.f, lev.phi);
+
+        // Level 1: row r from global memory.
+        {
+            const WalkRow w = walk_row(r, ny, a.pery);
+            const int n = w.y * a.pitch + x;
+            const T phi = collide<T, SRC, KPHI>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, x, w.y));
+            F::settle(a, lev.f, phi);
+            lev.phi = phi;
+            // Keep level 1 (and so the wait for its loads) ahead of the stores below.
+            asm volatile("" ::"v"(lev.f[0]), "v"(lev.f[1]), "v"(lev.f[2]), "v"(lev.f[3]), "v"(lev.f[4]),
+                         "v"(lev.f[5]), "v"(lev.f[6]), "v"(lev.f[7]), "v"(lev.f[8]), "v"(phi)
+                         : "memory");
+        }
+        if (out_n >= 0) F::put(a, out_n, out.f, out.phi);
+        out_n = -1;
+        if (r + 1 < r1) walk_load<F>(a, x, colok, r + 1, in);
+
+        // Levels 2..K: row r-(l-1) from the carried rows of level l-1.
+#pragma unroll
+        for (int l = 2; l <= K; ++l) {
+            const int q = r - (l - 1);
+            const WalkRow w = walk_row(q, ny, a.pery);
+            T g[9];
+            const T phi = walk_collide<T, SRC, KPHI>(a, carry[l - 2], lev, x, okxm, okxp, w, g);
+            if (l < K) {
+                F::settle(a, g, phi);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lev.f[i] = g[i];
+                lev.phi = phi;
+            } else if (store_col && q >= ys && q < ye) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) out.f[i] = g[i];
+                out.phi = phi;
+                out_n = w.y * a.pitch + x;
+            }
+        }
+    }
+    if (out_n >= 0) F::put(a, out_n, out.f, out.phi);
 }
 
 // ---- many instances in one launch -------------------------------------------------------
@@ -476,38 +787,144 @@ __global__ __launch_bounds__(kBlock) void reduce_final_kernel(const double* __re
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
-template <typename F>
-hipError_t sweep_with(const SweepArgs<typename F::T>& a_in, int src_kind, bool k1_per_node, int steps, hipStream_t s)
+// Compute units of the current device (cached per device ordinal).
+int device_cus()
 {
-    using T = typename F::T;
-    SweepArgs<T> a = a_in;
-    if (steps == 2) {
-        a.tiles_x = (a.nx + kTile2X - 1) / kTile2X;
-        a.tiles_y = (a.ny + Tile2<T>::TY - 1) / Tile2<T>::TY;
-    } else {
-        a.tiles_x = (a.nx + kTileX - 1) / kTileX;
-        a.tiles_y = (a.ny + kTileY - 1) / kTileY;
+    static int cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
     }
-    const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
-#define BTRT_SWEEP(SRC, KP)                                                                                \
-    do {                                                                                                   \
-        if (steps == 2)                                                                                    \
-            hipLaunchKernelGGL((sweep2_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock2), 0, s, a);          \
-        else                                                                                               \
-            hipLaunchKernelGGL((sweep_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);            \
-    } while (0)
-    if (k1_per_node) {
-        if (src_kind == kSrcField) BTRT_SWEEP(kSrcField, true);
-        else if (src_kind == kSrcSep) BTRT_SWEEP(kSrcSep, true);
-        else BTRT_SWEEP(kSrcNone, true);
-    } else {
-        if (src_kind == kSrcField) BTRT_SWEEP(kSrcField, false);
-        else if (src_kind == kSrcSep) BTRT_SWEEP(kSrcSep, false);
-        else BTRT_SWEEP(kSrcNone, false);
+    return cache[dev];
+}
+
+// Resident wavefronts per CU of one walker instantiation (its registers decide).
+template <typename F, int SRC, bool KP, int K>
+int walk_waves_per_cu()
+{
+    static const int waves = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<F, SRC, KP, K>, kWave, 0) != hipSuccess ||
+            nb <= 0)
+            nb = 8;
+        return nb;
+    }();
+    return waves;
+}
+
+// Automatic launch shape (measured on gfx950 over 256^2 .. 4096^2 grids):
+//  - steps: 4 per launch from 2^20 nodes up (the state no longer fits the caches and the
+//    strip walkers cut its traffic), one per launch below;
+//  - strip rows: the largest of 32, 16, 8 that still gives every resident wavefront slot about
+//    two strips (rows at least 8);
+//  - strips per group: kWalkGroup with 32-row strips (large grids), else 1.
+template <typename F, int SRC, bool KP, int K>
+void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
+{
+    constexpr int W = Walk<K>::W;
+    const int64_t strips_x = (a.nx + W - 1) / W;
+    if (cfg.rows <= 0) {
+        const int64_t want = 2LL * device_cus() * walk_waves_per_cu<F, SRC, KP, K>();
+        cfg.rows = 8;
+        for (int r : {32, 16}) {
+            if (strips_x * ((a.ny + r - 1) / r) >= want) {
+                cfg.rows = r;
+                break;
+            }
+        }
     }
-#undef BTRT_SWEEP
+    if (cfg.group <= 0) cfg.group = cfg.rows >= 32 ? kWalkGroup : 1;
+}
+
+template <typename F, int SRC, bool KP>
+LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
+{
+    if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kMaxFuse : 1;
+    if (cfg.steps != 2) cfg.tile = 0;
+    if (cfg.steps == 1 || cfg.tile) {
+        cfg.rows = cfg.group = 0;
+        return cfg;
+    }
+    switch (cfg.steps) {
+        case 2: walk_shape<F, SRC, KP, 2>(a, cfg); break;
+        case 3: walk_shape<F, SRC, KP, 3>(a, cfg); break;
+        default: walk_shape<F, SRC, KP, 4>(a, cfg); break;
+    }
+    return cfg;
+}
+
+template <typename F, int SRC, bool KP, int K>
+hipError_t walk_launch(SweepArgs<typename F::T> a, const LaunchCfg& cfg, hipStream_t s)
+{
+    constexpr int W = Walk<K>::W;
+    a.tiles_x = (a.nx + W - 1) / W;
+    a.rows = cfg.rows;
+    a.tiles_y = (a.ny + a.rows - 1) / a.rows;
+    const int groups_x = (a.tiles_x + cfg.group - 1) / cfg.group;
+    const unsigned grid = static_cast<unsigned>(groups_x) * static_cast<unsigned>(a.tiles_y);
+    hipLaunchKernelGGL((walk_kernel<F, SRC, KP, K>), dim3(grid), dim3(kWave * cfg.group), 0, s, a);
     return hipGetLastError();
 }
+
+template <typename F, int SRC, bool KP>
+hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t s)
+{
+    using T = typename F::T;
+    cfg = resolve_variant<F, SRC, KP>(a, cfg);
+    if (cfg.steps < 1 || cfg.steps > kMaxFuse || cfg.rows < 0 || (cfg.steps >= 2 && !cfg.tile && cfg.rows < 1) ||
+        (cfg.group != 0 && cfg.group != 1 && cfg.group != kWalkGroup))
+        return hipErrorInvalidValue;
+    if (cfg.steps == 1) {
+        a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+        a.tiles_y = (a.ny + kTileY - 1) / kTileY;
+        const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
+        hipLaunchKernelGGL((sweep_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    if (cfg.tile) {
+        a.tiles_x = (a.nx + kTile2X - 1) / kTile2X;
+        a.tiles_y = (a.ny + Tile2<T>::TY - 1) / Tile2<T>::TY;
+        const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
+        hipLaunchKernelGGL((sweep2_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock2), 0, s, a);
+        return hipGetLastError();
+    }
+    switch (cfg.steps) {
+        case 2: return walk_launch<F, SRC, KP, 2>(a, cfg, s);
+        case 3: return walk_launch<F, SRC, KP, 3>(a, cfg, s);
+        default: return walk_launch<F, SRC, KP, 4>(a, cfg, s);
+    }
+}
+
+// Source kind x per-node K1 dispatch of FN<F, SRC, KP>(args...).
+#define BTRT_BY_VARIANT(FN, ...)                                                   \
+    do {                                                                           \
+        if (k1_per_node) {                                                         \
+            if (src_kind == kSrcField) return FN<F, kSrcField, true>(__VA_ARGS__); \
+            if (src_kind == kSrcSep) return FN<F, kSrcSep, true>(__VA_ARGS__);     \
+            return FN<F, kSrcNone, true>(__VA_ARGS__);                             \
+        }                                                                          \
+        if (src_kind == kSrcField) return FN<F, kSrcField, false>(__VA_ARGS__);    \
+        if (src_kind == kSrcSep) return FN<F, kSrcSep, false>(__VA_ARGS__);        \
+        return FN<F, kSrcNone, false>(__VA_ARGS__);                                \
+    } while (0)
+
+template <typename F>
+hipError_t sweep_with(const SweepArgs<typename F::T>& a, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+                      hipStream_t s)
+{
+    BTRT_BY_VARIANT(sweep_variant, a, cfg, s);
+}
+
+template <typename F>
+LaunchCfg resolve_with(const SweepArgs<typename F::T>& a, int src_kind, bool k1_per_node, const LaunchCfg& cfg)
+{
+    BTRT_BY_VARIANT(resolve_variant, a, cfg);
+}
+
+#undef BTRT_BY_VARIANT
 
 template <typename F>
 hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], double ax, double ay,
@@ -558,9 +975,22 @@ hipError_t reduce_with(const GatherArgs<typename F::T>& a, int mode, double* res
     } while (0)
 
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, int steps, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+                        hipStream_t s)
 {
-    BTRT_BY_FORMAT(T, sweep_with, a, src_kind, k1_per_node, steps, s);
+    BTRT_BY_FORMAT(T, sweep_with, a, src_kind, k1_per_node, cfg, s);
+}
+
+template <typename T>
+LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, LaunchCfg cfg)
+{
+    if constexpr (sizeof(T) == 8) {
+        return resolve_with<Plain<T>>(a, src_kind, k1_per_node, cfg);
+    } else {
+        if (fmt == kFmtF16Dev) return resolve_with<Dev<F16Codec>>(a, src_kind, k1_per_node, cfg);
+        if (fmt == kFmtBF16Dev) return resolve_with<Dev<BF16Codec>>(a, src_kind, k1_per_node, cfg);
+        return resolve_with<Plain<T>>(a, src_kind, k1_per_node, cfg);
+    }
 }
 
 template <typename T>
@@ -612,7 +1042,8 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
 }
 
 #define BTRT_INSTANTIATE(T)                                                                                        \
-    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, bool, int, hipStream_t);                   \
+    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, bool, const LaunchCfg&, hipStream_t);      \
+    template LaunchCfg resolve_launch<T>(const SweepArgs<T>&, int, int, bool, LaunchCfg);                        \
     template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], double, double,   \
                                        double, double, hipStream_t);                                               \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, int, hipStream_t);                           \

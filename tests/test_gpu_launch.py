@@ -1,0 +1,90 @@
+"""Launch shapes of the sweep (btrt_set_launch / btrt_get_launch / btrt_tune).
+
+Every shape must give the bits of one step per launch: the strip walkers over steps per launch,
+strip rows and strips per group, and the two-step LDS tile, on a grid with every kind of
+boundary and on a periodic one, with step counts that end in a shorter launch. The tuner runs
+real steps on the live state, so after tuning the state must equal plain stepping by the
+same number of steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1902_09813_amd import btrt
+from paper_1902_09813_amd import workloads as W
+from tests.test_gpu_parity import custom
+
+pytestmark = pytest.mark.gpu
+
+# The tuner's candidate shapes: (steps_per_launch, strip_rows, strips_per_group, tile).
+SHAPES = [(1, 0, 0, 0), (2, 0, 0, 1)] + [(k, r, g, 0) for k in (2, 3, 4) for r in (8, 16, 32, 64, 128) for g in (1, 4)]
+
+GRIDS = [
+    custom("walls_mixed", 150, 83, 0, bc_type=(1, 1, 0, 0), bc_value=(0.3, 0.8, 0, 0), flux_b=(0.04, -0.03),
+           beta=0.5, source=("sin", 0.003, 1, 2)),
+    custom("periodic_aniso", 131, 70, 0, flux_b=(0.02, 0.03), beta=0.3),
+]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("precision", [btrt.F64, btrt.F32, btrt.F16DEV], ids=["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("w", GRIDS, ids=lambda w: w.name)
+def test_every_launch_shape_is_bitwise_identical(w, precision):
+    steps = 2 * 4 * 3 + 1
+    say(f"[gpu] launch shapes {w.name} {w.nx}x{w.ny} prec={precision} steps={steps}")
+    with btrt.Solver(btrt.problem_from_workload(w, precision=precision), w.phi0()) as ref:
+        ref.set_fusion(1).step(steps)
+        want_f, want_phi = ref.populations(), ref.field()
+    for shape in SHAPES:
+        with btrt.Solver(btrt.problem_from_workload(w, precision=precision), w.phi0()) as s:
+            s.set_launch(*shape).step(steps)
+            assert np.array_equal(s.populations(), want_f), shape
+            assert np.array_equal(s.field(), want_phi), shape
+
+
+@pytest.mark.parametrize("w", [GRIDS[0], W.c3().scaled(512, 512, 0)], ids=["walls_mixed", "c3_512"])
+def test_tune_advances_the_state_like_plain_steps(w):
+    say(f"[gpu] tune {w.name} {w.nx}x{w.ny}")
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
+        shape, used = s.tune(400)
+        assert 0 < used <= 400
+        assert s.info().step == used
+        assert s.launch() == shape
+        k, rows, group, tile = shape
+        assert 1 <= k <= 4 and group in (0, 1, 4) and tile in (0, 1)
+        s.step(13)
+        got = s.populations()
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as r:
+        r.set_fusion(1).step(used + 13)
+        assert np.array_equal(r.populations(), got)
+
+
+def test_tune_with_too_few_steps_keeps_the_shape():
+    w = W.c1(1.0)
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
+        before = s.launch()
+        shape, used = s.tune(2)  # one candidate (one step per launch, 3 steps) does not fit
+        assert used == 0 and shape == before and s.info().step == 0
+
+
+def test_automatic_shape_by_grid_size():
+    with btrt.Solver(btrt.problem_from_workload(W.c1(1.0)), W.c1(1.0).phi0()) as s:
+        assert s.launch() == (1, 0, 0, 0)  # 64 x 64: one step per launch
+    w = W.c2()
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
+        k, rows, group, tile = s.launch()
+        assert k == 4 and rows in (8, 16, 32) and group in (1, 4) and tile == 0
+
+
+def test_invalid_launch_shapes_are_rejected():
+    w = W.c1(1.0)
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
+        for bad in [(5, 0, 0, 0), (-1, 0, 0, 0), (2, -1, 0, 0), (2, 16, 3, 0), (3, 0, 0, 1), (1, 0, 0, 1)]:
+            with pytest.raises(btrt.BtrtError) as e:
+                s.set_launch(*bad)
+            assert e.value.code == btrt.E_INVAL, bad

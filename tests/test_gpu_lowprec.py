@@ -2,8 +2,8 @@
 
 The populations are stored as 16-bit values of s * (f+ - f_eq(phi)) with phi kept in FP32 and
 s a power of two fixed at set-up; the arithmetic is FP32. Checked here:
-  * two steps per launch give the bits of two single steps, for every boundary combination
-    (the fused kernel applies the same 16-bit round trip to the tile it keeps on chip);
+  * k steps per launch give the bits of k single steps, for every boundary combination
+    (the fused kernel applies the same 16-bit round trip to the levels it keeps on chip);
   * splitting a run into several calls does not change a bit;
   * the initial populations are f_eq(phi0) (Section 4) within the rounding of the stored
     deviations, element by element;
@@ -37,14 +37,15 @@ def solver(w, precision):
     return btrt.Solver(btrt.problem_from_workload(w, precision=precision), w.phi0())
 
 
+@pytest.mark.parametrize("k", [2, 4])
 @pytest.mark.parametrize("precision", FORMATS, ids=lambda p: FMT_ID[p])
 @pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
-def test_fused_two_step_launch_is_bitwise_identical(w, precision):
+def test_fused_launch_is_bitwise_identical(w, precision, k):
     steps = min(w.steps, 151) | 1
-    say(f"[gpu] {FMT_ID[precision]} fused vs single {w.name} {w.nx}x{w.ny} steps={steps}")
+    say(f"[gpu] {FMT_ID[precision]} fused {k} vs single {w.name} {w.nx}x{w.ny} steps={steps}")
     with solver(w, precision) as a, solver(w, precision) as b:
         a.set_fusion(1).step(steps)
-        b.set_fusion(2).step(steps)
+        b.set_fusion(k).step(steps)
         assert np.array_equal(a.populations(), b.populations())
         assert np.array_equal(a.field(), b.field())
 

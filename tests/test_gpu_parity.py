@@ -139,18 +139,51 @@ def test_torch_memory_and_stream_bitwise_identical(w):
     assert np.array_equal(pa, pb)
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
 @pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
-def test_fused_two_step_launch_is_bitwise_identical(w):
-    # Two steps per launch through the on-chip tile must give the bits of two single steps,
-    # for every boundary combination and an odd number of steps.
+def test_fused_launch_is_bitwise_identical(w, k):
+    # k steps per launch (strip walkers, intermediate levels in registers) must give the bits
+    # of k single steps, for every boundary combination and a step count that ends with a
+    # shorter launch.
     steps = min(w.steps, 151) | 1
-    say(f"[gpu] fused vs single {w.name} {w.nx}x{w.ny} steps={steps}")
+    say(f"[gpu] fused {k} vs single {w.name} {w.nx}x{w.ny} steps={steps}")
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as a, \
             btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as b:
         a.set_fusion(1).step(steps)
-        b.set_fusion(2).step(steps)
+        b.set_fusion(k).step(steps)
         assert np.array_equal(a.populations(), b.populations())
         assert np.array_equal(a.field(), b.field())
+
+
+# Shapes around the walker's strip width (66 - 2k columns) and strip height (16 rows at these
+# sizes), with every boundary combination.
+WALK_SHAPES = [(57, 17), (58, 16), (59, 33), (60, 31), (62, 47), (116, 15), (125, 64), (1, 40), (130, 1), (3, 3)]
+WALK_BCS = [(0, 0, 0, 0), (1, 1, 1, 1), (0, 0, 1, 1), (1, 1, 0, 0)]
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("shape", WALK_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_walker_strip_edges_bitwise(shape, k):
+    nx, ny = shape
+    for bc in WALK_BCS:
+        w = custom(f"walk_{nx}x{ny}", nx, ny, 0, bc_type=bc, bc_value=(0.2, 0.7, 0.4, 0.9), flux_b=(0.04, -0.03),
+                   beta=0.5, source=("sin", 0.003, 1, 2))
+        steps = 3 * k + 1
+        say(f"[gpu] walker k={k} {nx}x{ny} bc={bc} steps={steps}")
+        with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as a, \
+                btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as b:
+            a.set_fusion(1).step(steps)
+            b.set_fusion(k).step(steps)
+            assert np.array_equal(a.populations(), b.populations()), bc
+
+
+def test_fusion_outside_range_is_rejected():
+    w = W.c1(1.0)
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
+        for k in (0, 5, -1):
+            with pytest.raises(btrt.BtrtError) as e:
+                s.set_fusion(k)
+            assert e.value.code == btrt.E_INVAL
 
 
 def test_step_split_is_bitwise_invariant():
