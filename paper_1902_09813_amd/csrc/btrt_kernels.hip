@@ -356,12 +356,16 @@ struct Level {
     T phi;
 };
 
-// What level l+1 keeps of level l between iterations: the populations of the row below the
-// one it updates next that move up (2, 5, 6), and that row itself.
-template <typename T>
-struct Carry {
-    T up2, up5, up6;
-    Level<T> mid;
+// What a walker lane keeps between rows. For each level l < K: the populations of the row
+// below the one level l+1 updates next that move up (2, 5, 6), and that row itself, in one of
+// two buffers that alternate from row to row (so no row is copied); and the last level's row
+// waiting to be stored.
+template <typename T, int K>
+struct WalkState {
+    T up[K - 1][3];
+    Level<T> mid[2][K - 1];
+    Level<T> out;
+    int out_n;  // node index of `out`, -1 when nothing waits
 };
 
 // Row coordinate of a walker: wrapped into the grid (periodic), with validity and wall flags.
@@ -388,38 +392,37 @@ __device__ __forceinline__ WalkRow walk_row(int q, int ny, int pery)
     return w;
 }
 
-// Level l >= 2 at one node: pull from the carried rows of level l-1 and the row it has just
-// produced (`fresh`), collide; the carry advances by one row. All lanes must be active here
-// (the wavefront shifts read the neighbouring lanes).
-template <typename T, int SRC, bool KPHI>
-__device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, Carry<T>& c, const Level<T>& fresh, int x, bool okxm,
-                                          bool okxp, const WalkRow& row, T g[9])
+// Level l >= 2 at one node: pull from level l-1's rows below (up: populations 2, 5, 6), at
+// (mid) and above (fresh, just produced), then collide. All lanes must be active here (the
+// wavefront shifts read the neighbouring lanes).
+template <typename T, int SRC, bool KPHI, bool WALLS>
+__device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], const Level<T>& mid,
+                                          const Level<T>& fresh, int x, bool okxm, bool okxp, const WalkRow& row,
+                                          T g[9])
 {
-    const T s1 = lane_shift<kShr1>(c.mid.f[1]);
-    const T s3 = lane_shift<kShl1>(c.mid.f[3]);
-    const T s5 = lane_shift<kShr1>(c.up5);
-    const T s6 = lane_shift<kShl1>(c.up6);
+    const T* m = mid.f;
+    const T s1 = lane_shift<kShr1>(m[1]);
+    const T s3 = lane_shift<kShl1>(m[3]);
+    const T s5 = lane_shift<kShr1>(up[1]);
+    const T s6 = lane_shift<kShl1>(up[2]);
     const T s7 = lane_shift<kShl1>(fresh.f[7]);
     const T s8 = lane_shift<kShr1>(fresh.f[8]);
-    const T* m = c.mid.f;
-    const bool okym = row.okm, okyp = row.okp;
+    if constexpr (!WALLS) {  // periodic in both directions: no bounce-back
+        okxm = okxp = true;
+    }
+    const bool okym = WALLS ? row.okm : true, okyp = WALLS ? row.okp : true;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
     g[0] = m[0];
     g[1] = okxm ? s1 : bounce(m[3], tw1, a.wall[0]);
-    g[2] = okym ? c.up2 : bounce(m[4], tw1, a.wall[2]);
+    g[2] = okym ? up[0] : bounce(m[4], tw1, a.wall[2]);
     g[3] = okxp ? s3 : bounce(m[1], tw1, a.wall[1]);
     g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, a.wall[3]);
     g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
     g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
     g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
     g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
-    const T phi_prev = c.mid.phi;
-    c.up2 = m[2];
-    c.up5 = m[5];
-    c.up6 = m[6];
-    c.mid = fresh;
     const int n = row.y * a.pitch + x;
-    return collide<T, SRC, KPHI>(a, g, phi_prev, source_at<T, SRC>(a, n, x, row.y));
+    return collide<T, SRC, KPHI>(a, g, mid.phi, source_at<T, SRC>(a, n, x, row.y));
 }
 
 // Level-1 inputs of row r at column x, as raw loads: for each direction the source address is
@@ -433,17 +436,24 @@ struct WalkIn {
     int ok;             // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
 };
 
-template <typename F>
+template <typename F, bool WALLS>
 __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int x, bool colok, int r, WalkIn<F>& in)
 {
-    const WalkRow w = walk_row(r, a.ny, a.pery);
+    const WalkRow w = walk_row(r, a.ny, WALLS ? a.pery : 1);
     const int nx = a.nx, ny = a.ny, pitch = a.pitch, y = w.y;
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
     bool okxm = true, okxp = true, okym = true, okyp = true;
-    if (xm < 0) { if (a.perx) xm += nx; else { okxm = false; xm = x; } }
-    if (xp >= nx) { if (a.perx) xp -= nx; else { okxp = false; xp = x; } }
-    if (ym < 0) { if (a.pery) ym += ny; else { okym = false; ym = y; } }
-    if (yp >= ny) { if (a.pery) yp -= ny; else { okyp = false; yp = y; } }
+    if constexpr (WALLS) {
+        if (xm < 0) { if (a.perx) xm += nx; else { okxm = false; xm = x; } }
+        if (xp >= nx) { if (a.perx) xp -= nx; else { okxp = false; xp = x; } }
+        if (ym < 0) { if (a.pery) ym += ny; else { okym = false; ym = y; } }
+        if (yp >= ny) { if (a.pery) yp -= ny; else { okyp = false; yp = y; } }
+    } else {
+        if (xm < 0) xm += nx;
+        if (xp >= nx) xp -= nx;
+        if (ym < 0) ym += ny;
+        if (yp >= ny) yp -= ny;
+    }
     const int n = y * pitch + x, r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
     const bool ok5 = okxm && okym, ok6 = okxp && okym, ok7 = okxp && okyp, ok8 = okxm && okyp;
     const int plane[9] = {0, okxm ? 1 : 3, okym ? 2 : 4, okxp ? 3 : 1, okyp ? 4 : 2,
@@ -457,11 +467,17 @@ __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int
 
 // f(x, t) from the raw loads (bounce-back at Dirichlet walls, Eqs. (54)-(56)); zeros where the
 // lane is not a node.
-template <typename F>
+template <typename F, bool WALLS>
 __device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, const WalkIn<F>& in,
                                             typename F::T f[9], typename F::T& phi_prev)
 {
     using T = typename F::T;
+    if constexpr (!WALLS) {  // periodic in both directions: every lane pulls from its neighbours
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = F::value(a, in.raw, i, i, false);
+        phi_prev = in.phi;
+        return;
+    }
     const bool okxm = in.ok & 1, okxp = in.ok & 2, okym = in.ok & 4, okyp = in.ok & 8, node = in.ok & 16;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
     const bool ok[9] = {true, okxm, okym, okxp, okyp, okxm && okym, okxp && okym, okxp && okyp, okxm && okyp};
@@ -489,7 +505,89 @@ __device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, c
 // A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
 // in one band of rows; they walk in lockstep (one barrier per row, no memory fence: they share
 // no data), so the rows they read and write at a time are contiguous across the group.
-template <typename F, int SRC, bool KPHI, int K>
+// Where a walker lane sits: its column, the band of rows of its strip and what it stores.
+struct WalkLane {
+    int x;                  // grid column of the lane (wrapped; clamped when not a node)
+    bool colok;             // the lane's column is a node of a live strip
+    bool okxm, okxp;        // x-1 / x+1 are nodes (else bounce-back at the x- / x+ wall)
+    bool store_col;         // the lane's column is an output column of its strip
+    int ys, ye;             // output rows ys .. ye-1
+};
+
+// Rows of level-1 loads in flight per walker: two for the 4- and 2-byte formats; one for FP64,
+// whose registers already limit a SIMD to two wavefronts (measured on gfx950: a second FP64 row
+// buys nothing and costs an occupancy step with Dirichlet walls).
+template <typename T>
+constexpr int kAhead = sizeof(T) == 8 ? 1 : 2;
+
+// One row of the walk: level 1 on row r, levels 2..K on rows r-1 .. r-(K-1). PH picks which
+// of the two row buffers per level is current; the next call uses the other. `in` holds the
+// loads of row r and receives those of row r + kAhead.
+template <typename F, int SRC, bool KPHI, int K, bool WALLS, int PH>
+__device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, const WalkLane& L, int r, int r1,
+                                          WalkIn<F>& in, WalkState<typename F::T, K>& st)
+{
+    using T = typename F::T;
+    __builtin_amdgcn_s_barrier();
+    Level<T> lev;
+    walk_finish<F, WALLS>(a, in, lev.f, lev.phi);
+
+    // Level 1: row r from global memory.
+    {
+        const WalkRow w = walk_row(r, a.ny, a.pery);
+        const int n = w.y * a.pitch + L.x;
+        const T phi = collide<T, SRC, KPHI>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y));
+        F::settle(a, lev.f, phi);
+        lev.phi = phi;
+        // Keep level 1 (and so the wait for its loads) ahead of the stores below.
+        asm volatile("" ::"v"(lev.f[0]), "v"(lev.f[1]), "v"(lev.f[2]), "v"(lev.f[3]), "v"(lev.f[4]), "v"(lev.f[5]),
+                     "v"(lev.f[6]), "v"(lev.f[7]), "v"(lev.f[8]), "v"(phi)
+                     : "memory");
+    }
+    // The last level's row from the previous call, then the loads two rows ahead: every wait
+    // covers memory operations issued at least one row earlier.
+    if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
+    st.out_n = -1;
+    if (r + kAhead<T> < r1) walk_load<F, WALLS>(a, L.x, L.colok, r + kAhead<T>, in);
+
+    // Levels 2..K: row r-(l-1) from the rows of level l-1. Level l is valid from row
+    // ys-(K-l) on; the first rows of the walk (while the levels fill) are skipped, which leaves
+    // only rows that no valid node reads.
+#pragma unroll
+    for (int l = 2; l <= K; ++l) {
+        const int q = r - (l - 1);
+        const WalkRow w = walk_row(q, a.ny, a.pery);
+        Level<T>& cur = st.mid[PH][l - 2];
+        T g[9];
+        T phi = T(0);
+        if (q >= L.ys - (K - l)) {
+            phi = walk_collide<T, SRC, KPHI, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, g);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = T(0);
+        }
+        st.up[l - 2][0] = cur.f[2];
+        st.up[l - 2][1] = cur.f[5];
+        st.up[l - 2][2] = cur.f[6];
+        st.mid[1 - PH][l - 2] = lev;
+        if (l < K) {
+            F::settle(a, g, phi);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lev.f[i] = g[i];
+            lev.phi = phi;
+        } else if (L.store_col && q >= L.ys && q < L.ye) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st.out.f[i] = g[i];
+            st.out.phi = phi;
+            st.out_n = w.y * a.pitch + L.x;
+        }
+    }
+}
+
+// A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
+// in one band of rows; they walk in lockstep (one barrier per row, no memory fence: they share
+// no data), so the rows they read and write at a time are contiguous across the group.
+template <typename F, int SRC, bool KPHI, int K, bool WALLS>
 __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typename F::T> a)
 {
     using T = typename F::T;
@@ -504,82 +602,45 @@ __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typen
     const int nx = a.nx, ny = a.ny;
 
     // Column of this lane (K-1 halo columns on each side of the strip).
-    const int xs = sx * W;
-    const int cx = xs - (K - 1) + lane;
-    int x;
-    bool colok;
+    WalkLane L;
+    const int cx = sx * W - (K - 1) + lane;
     if (a.perx) {
-        x = wrap(cx, nx);
-        colok = live;
+        L.x = wrap(cx, nx);
+        L.colok = live;
     } else {
-        colok = live && cx >= 0 && cx < nx;
-        x = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx);
+        L.colok = live && cx >= 0 && cx < nx;
+        L.x = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx);
     }
-    const bool okxm = a.perx || x > 0, okxp = a.perx || x < nx - 1;
-    const bool store_col = live && lane >= K - 1 && lane < kWave - (K - 1) && cx < nx;
+    L.okxm = a.perx || L.x > 0;
+    L.okxp = a.perx || L.x < nx - 1;
+    L.store_col = live && lane >= K - 1 && lane < kWave - (K - 1) && cx < nx;
+    L.ys = sy * a.rows;
+    L.ye = min(L.ys + a.rows, ny);  // uniform over the group
+    const int r0 = L.ys - (K - 1), r1 = L.ye + (K - 1);
 
-    const int ys = sy * a.rows;
-    const int ye = min(ys + a.rows, ny);  // output rows ys .. ye-1 (uniform over the group)
-    const int r0 = ys - (K - 1), r1 = ye + (K - 1);
-
-    Carry<T> carry[K - 1];
+    WalkState<T, K> st;
 #pragma unroll
     for (int l = 0; l < K - 1; ++l) {
-        carry[l].up2 = carry[l].up5 = carry[l].up6 = T(0);
+        st.up[l][0] = st.up[l][1] = st.up[l][2] = T(0);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) carry[l].mid.f[i] = T(0);
-        carry[l].mid.phi = T(0);
-    }
-
-    // Level-1 loads run one row ahead. The last level's row is stored one iteration late, after
-    // level 1 has consumed the loads and just before the next loads are issued, so every wait
-    // covers memory operations issued a full iteration earlier.
-    WalkIn<F> in;
-    walk_load<F>(a, x, colok, r0, in);
-    Level<T> out;
-    int out_n = -1;
-    for (int r = r0; r < r1; ++r) {
-        __builtin_amdgcn_s_barrier();
-        Level<T> lev;
-        walk_finish<F>(a, in, lev.f, lev.phi);
-
-        // Level 1: row r from global memory.
-        {
-            const WalkRow w = walk_row(r, ny, a.pery);
-            const int n = w.y * a.pitch + x;
-            const T phi = collide<T, SRC, KPHI>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, x, w.y));
-            F::settle(a, lev.f, phi);
-            lev.phi = phi;
-            // Keep level 1 (and so the wait for its loads) ahead of the stores below.
-            asm volatile("" ::"v"(lev.f[0]), "v"(lev.f[1]), "v"(lev.f[2]), "v"(lev.f[3]), "v"(lev.f[4]),
-                         "v"(lev.f[5]), "v"(lev.f[6]), "v"(lev.f[7]), "v"(lev.f[8]), "v"(phi)
-                         : "memory");
-        }
-        if (out_n >= 0) F::put(a, out_n, out.f, out.phi);
-        out_n = -1;
-        if (r + 1 < r1) walk_load<F>(a, x, colok, r + 1, in);
-
-        // Levels 2..K: row r-(l-1) from the carried rows of level l-1.
+        for (int b = 0; b < 2; ++b) {
 #pragma unroll
-        for (int l = 2; l <= K; ++l) {
-            const int q = r - (l - 1);
-            const WalkRow w = walk_row(q, ny, a.pery);
-            T g[9];
-            const T phi = walk_collide<T, SRC, KPHI>(a, carry[l - 2], lev, x, okxm, okxp, w, g);
-            if (l < K) {
-                F::settle(a, g, phi);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) lev.f[i] = g[i];
-                lev.phi = phi;
-            } else if (store_col && q >= ys && q < ye) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) out.f[i] = g[i];
-                out.phi = phi;
-                out_n = w.y * a.pitch + x;
-            }
+            for (int i = 0; i < 9; ++i) st.mid[b][l].f[i] = T(0);
+            st.mid[b][l].phi = T(0);
         }
     }
-    if (out_n >= 0) F::put(a, out_n, out.f, out.phi);
+    st.out_n = -1;
+
+    // Loads of rows r0, r0+2, ... go to in[0] and of rows r0+1, r0+3, ... to in[1] with two
+    // rows in flight; with one row in flight in[0] serves every row.
+    WalkIn<F> in[kAhead<T>];
+    walk_load<F, WALLS>(a, L.x, L.colok, r0, in[0]);
+    if (kAhead<T> == 2 && r0 + 1 < r1) walk_load<F, WALLS>(a, L.x, L.colok, r0 + 1, in[kAhead<T> - 1]);
+    for (int r = r0; r < r1; r += 2) {
+        walk_step<F, SRC, KPHI, K, WALLS, 0>(a, L, r, r1, in[0], st);
+        if (r + 1 < r1) walk_step<F, SRC, KPHI, K, WALLS, 1>(a, L, r + 1, r1, in[kAhead<T> - 1], st);
+    }
+    if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
 }
 
 // ---- many instances in one launch -------------------------------------------------------
@@ -807,7 +868,7 @@ int walk_waves_per_cu()
 {
     static const int waves = [] {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<F, SRC, KP, K>, kWave, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<F, SRC, KP, K, true>, kWave, 0) != hipSuccess ||
             nb <= 0)
             nb = 8;
         return nb;
@@ -865,7 +926,10 @@ hipError_t walk_launch(SweepArgs<typename F::T> a, const LaunchCfg& cfg, hipStre
     a.tiles_y = (a.ny + a.rows - 1) / a.rows;
     const int groups_x = (a.tiles_x + cfg.group - 1) / cfg.group;
     const unsigned grid = static_cast<unsigned>(groups_x) * static_cast<unsigned>(a.tiles_y);
-    hipLaunchKernelGGL((walk_kernel<F, SRC, KP, K>), dim3(grid), dim3(kWave * cfg.group), 0, s, a);
+    if (a.perx && a.pery)
+        hipLaunchKernelGGL((walk_kernel<F, SRC, KP, K, false>), dim3(grid), dim3(kWave * cfg.group), 0, s, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<F, SRC, KP, K, true>), dim3(grid), dim3(kWave * cfg.group), 0, s, a);
     return hipGetLastError();
 }
 
