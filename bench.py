@@ -47,11 +47,12 @@ def sweep_launches(steps, fusion):
     return n
 
 
-def timed_run(w, precision, steps, warmup, fusion=0):
+def timed_run(w, precision, steps, warmup, fusion=0, launch=None):
     """Warm up, then time exactly ``steps`` steps with HIP events on the library's stream.
 
     fusion 0: the warm-up starts with btrt_tune (real steps on the live state, at most 300)
-    and the fastest launch shape is kept; 1..4: that many steps per launch, automatic strips."""
+    and the fastest launch shape is kept; 1..4: that many steps per launch, automatic strips.
+    launch: a fixed (steps_per_launch, strip_rows, strips_per_group, tile) instead."""
     import torch
     from paper_1902_09813_amd import btrt
 
@@ -60,7 +61,9 @@ def timed_run(w, precision, steps, warmup, fusion=0):
     stream = solver.torch_stream  # the stream every kernel of the solver is launched on
     info = solver.info()
     tuned = 0
-    if fusion:
+    if launch:
+        solver.set_launch(*launch)
+    elif fusion:
         solver.set_fusion(fusion)
     else:
         _, tuned = solver.tune(300)
@@ -280,6 +283,8 @@ def main():
     ap.add_argument("--precision", choices=["f64", "f32", "f16dev", "bf16dev"], default="f64")
     ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4], default=0,
                     help="time steps per sweep launch (0: tuned during the warm-up)")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch shape steps,rows,group,tile for the main measurement (default: tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
@@ -310,7 +315,8 @@ def main():
     w = W.c3()
     print(f"[bench] {w.name} {args.precision}: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr,
           flush=True)
-    r = timed_run(w, prec, args.steps, args.warmup, args.fusion)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    r = timed_run(w, prec, args.steps, args.warmup, args.fusion, launch)
     bytes_per_launch = r["bytes_per_node_launch"] * r["nodes"]
     achieved = bytes_per_launch / (r["launch_ms_avg"] * 1e-3) / 1e9
     roofline = {

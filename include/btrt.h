@@ -170,7 +170,8 @@ int btrt_step(btrt_t* h, int64_t n);
  *                     keeps the k - 1 intermediate time levels in registers, so the state is
  *                     read and written once per k steps. Step counts that are not a multiple of
  *                     k end with one shorter launch.
- *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size)
+ *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size);
+ *                     with one step per launch, the tile height 1, 2, 4, 8 or 16 (0: 4)
  *   strips_per_group  1 or 4 strips per workgroup, walked side by side in lockstep (0: auto)
  *   tile              1 with steps_per_launch 2: the two-step LDS tile kernel instead of a
  *                     strip walker (tiles of 64 x 8 nodes in FP64, 64 x 16 otherwise) */
@@ -182,7 +183,8 @@ typedef struct {
 } btrt_launch_t;
 
 /* Sets the launch shape; fields as above. Errors: BTRT_E_INVAL (steps outside [0, 4],
- * strip_rows < 0, strips_per_group not 0, 1 or 4, tile without steps_per_launch 2). */
+ * strip_rows < 0 or, with one step per launch, not 0, 1, 2, 4, 8 or 16, strips_per_group not
+ * 0, 1 or 4, tile without steps_per_launch 2). */
 int btrt_set_launch(btrt_t* h, const btrt_launch_t* cfg);
 
 /* The launch shape in force, with the automatic fields resolved for this grid. */
@@ -193,7 +195,7 @@ int btrt_get_launch(btrt_t* h, btrt_launch_t* cfg);
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch);
 
 /* Times candidate launch shapes on the handle's own state and keeps the fastest (per step):
- * one step per launch, the LDS tile, and strip walkers over 2 .. 4 steps x 8, 16, 32, 64, 128 rows
+ * one step per launch (tiles of 4, 8, 16 rows), the LDS tile, and strip walkers over 2 .. 4 steps x 8, 16, 32, 64, 128 rows
  * x 1, 4 strips per group, each for one untimed and two timed launches, as far as max_steps
  * allows. The state advances by *steps_used steps (the same bits btrt_step would give);
  * the Eq. (64) snapshot is not touched. Synchronises. best (may be NULL) receives the shape

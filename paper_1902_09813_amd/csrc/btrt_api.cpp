@@ -41,6 +41,7 @@ int enqueue_steps(btrt* h, const LaunchCfg& want, int64_t n)
         LaunchCfg k = c;
         k.steps = static_cast<int>(std::min<int64_t>(c.steps, n - i));
         if (k.steps != 2) k.tile = 0;
+        if (k.steps == 1 && c.steps != 1) k.rows = k.group = 0;  // the one-step kernel's own tiles
         int rc = instance_launch(h->inst, k, h->stream);
         if (rc != BTRT_OK) return rc;
         i += k.steps;
@@ -52,6 +53,9 @@ int enqueue_steps(btrt* h, int64_t n) { return enqueue_steps(h, h->launch, n); }
 
 bool launch_ok(const btrt_launch_t* c)
 {
+    if (c && c->steps_per_launch == 1 && c->strip_rows != 0 &&
+        (c->strip_rows > 16 || (c->strip_rows & (c->strip_rows - 1))))
+        return false;  // one step per launch: tile height 1, 2, 4, 8 or 16 rows
     return c && c->steps_per_launch >= 0 && c->steps_per_launch <= btrtk::kMaxFuse && c->strip_rows >= 0 &&
            c->strip_rows <= (1 << 24) &&
            (c->strips_per_group == 0 || c->strips_per_group == 1 || c->strips_per_group == btrtk::kWalkGroup) &&
@@ -207,7 +211,7 @@ int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_
     DeviceGuard g(h->device);
     // Candidates: one step per launch, the two-step LDS tile, and strip walkers over steps per
     // launch x strip rows x strips per group. Each runs one untimed launch and kReps timed ones.
-    std::vector<LaunchCfg> cand{{1, 0, 0, 0}, {2, 0, 0, 1}};
+    std::vector<LaunchCfg> cand{{1, 4, 0, 0}, {1, 8, 0, 0}, {1, 16, 0, 0}, {2, 0, 0, 1}};
     for (int k = 2; k <= btrtk::kMaxFuse; ++k)
         for (int rows : {8, 16, 32, 64, 128})
             for (int grp : {1, btrtk::kWalkGroup}) cand.push_back(LaunchCfg{k, rows, grp, 0});

@@ -28,6 +28,7 @@ namespace {
 
 constexpr int kTileX = 64;  // one wavefront along a row: coalesced 64-wide accesses
 constexpr int kTileY = kBlock / kTileX;
+constexpr int kMaxBlock1 = 1024;  // one-step kernel: tiles of up to 64 x 16 nodes
 
 // Block index -> tile index, grouping consecutive tiles on one XCD. Workgroups are
 // dispatched round-robin over the 8 XCDs; this gives XCD k a contiguous run of tiles so
@@ -170,13 +171,13 @@ struct Dev {
 
 // ---- one time step --------------------------------------------------------------------------
 
-// One time step on tile (tx, ty) of kTileX x kTileY nodes, one node per thread.
+// One time step on tile (tx, ty) of kTileX x rows nodes, one node per thread.
 template <typename F, int SRC, bool KPHI>
-__device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx, int ty)
+__device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx, int ty, int rows)
 {
     using T = typename F::T;
     const int x = tx * kTileX + static_cast<int>(threadIdx.x % kTileX);
-    const int y = ty * kTileY + static_cast<int>(threadIdx.x / kTileX);
+    const int y = ty * rows + static_cast<int>(threadIdx.x / kTileX);
     if (x >= a.nx || y >= a.ny) return;
     T f[9];
     F::pull(a, x, y, f);
@@ -185,12 +186,14 @@ __device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx,
     F::put(a, n, f, phi);
 }
 
+// Tiles of 64 x (blockDim.x / 64) nodes; taller tiles re-read fewer halo rows of their
+// neighbours above and below.
 template <typename F, int SRC, bool KPHI>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename F::T> a)
+__global__ __launch_bounds__(kMaxBlock1) void sweep_kernel(SweepArgs<typename F::T> a)
 {
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
-    tile1<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty);
+    tile1<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, static_cast<int>(blockDim.x) / kTileX);
 }
 
 // Wrap a coordinate of a periodic direction into [0, n) (any distance).
@@ -674,12 +677,12 @@ __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __r
         const int tiles_x = (a.nx + kTileX - 1) / kTileX;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile1<F, kSrcNone, false>(a, tx, ty); break;
-            case 1: tile1<F, kSrcNone, true>(a, tx, ty); break;
-            case 2: tile1<F, kSrcField, false>(a, tx, ty); break;
-            case 3: tile1<F, kSrcField, true>(a, tx, ty); break;
-            case 4: tile1<F, kSrcSep, false>(a, tx, ty); break;
-            default: tile1<F, kSrcSep, true>(a, tx, ty); break;
+            case 0: tile1<F, kSrcNone, false>(a, tx, ty, kTileY); break;
+            case 1: tile1<F, kSrcNone, true>(a, tx, ty, kTileY); break;
+            case 2: tile1<F, kSrcField, false>(a, tx, ty, kTileY); break;
+            case 3: tile1<F, kSrcField, true>(a, tx, ty, kTileY); break;
+            case 4: tile1<F, kSrcSep, false>(a, tx, ty, kTileY); break;
+            default: tile1<F, kSrcSep, true>(a, tx, ty, kTileY); break;
         }
     }
 }
@@ -905,7 +908,12 @@ LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
 {
     if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kMaxFuse : 1;
     if (cfg.steps != 2) cfg.tile = 0;
-    if (cfg.steps == 1 || cfg.tile) {
+    if (cfg.steps == 1) {  // rows: tile height of the one-step kernel
+        if (cfg.rows <= 0) cfg.rows = kTileY;
+        cfg.group = 0;
+        return cfg;
+    }
+    if (cfg.tile) {
         cfg.rows = cfg.group = 0;
         return cfg;
     }
@@ -939,13 +947,14 @@ hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t 
     using T = typename F::T;
     cfg = resolve_variant<F, SRC, KP>(a, cfg);
     if (cfg.steps < 1 || cfg.steps > kMaxFuse || cfg.rows < 0 || (cfg.steps >= 2 && !cfg.tile && cfg.rows < 1) ||
+        (cfg.steps == 1 && (cfg.rows < 1 || cfg.rows > kMaxBlock1 / kTileX || (cfg.rows & (cfg.rows - 1)))) ||
         (cfg.group != 0 && cfg.group != 1 && cfg.group != kWalkGroup))
         return hipErrorInvalidValue;
     if (cfg.steps == 1) {
         a.tiles_x = (a.nx + kTileX - 1) / kTileX;
-        a.tiles_y = (a.ny + kTileY - 1) / kTileY;
+        a.tiles_y = (a.ny + cfg.rows - 1) / cfg.rows;
         const unsigned grid = static_cast<unsigned>(a.tiles_x) * static_cast<unsigned>(a.tiles_y);
-        hipLaunchKernelGGL((sweep_kernel<F, SRC, KP>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((sweep_kernel<F, SRC, KP>), dim3(grid), dim3(kTileX * cfg.rows), 0, s, a);
         return hipGetLastError();
     }
     if (cfg.tile) {

@@ -18,7 +18,7 @@ from tests.test_gpu_parity import custom
 pytestmark = pytest.mark.gpu
 
 # The tuner's candidate shapes: (steps_per_launch, strip_rows, strips_per_group, tile).
-SHAPES = [(1, 0, 0, 0), (2, 0, 0, 1)] + [(k, r, g, 0) for k in (2, 3, 4) for r in (8, 16, 32, 64, 128) for g in (1, 4)]
+SHAPES = [(1, 0, 0, 0), (1, 1, 0, 0), (1, 8, 0, 0), (1, 16, 0, 0), (2, 0, 0, 1)] + [(k, r, g, 0) for k in (2, 3, 4) for r in (8, 16, 32, 64, 128) for g in (1, 4)]
 
 GRIDS = [
     custom("walls_mixed", 150, 83, 0, bc_type=(1, 1, 0, 0), bc_value=(0.3, 0.8, 0, 0), flux_b=(0.04, -0.03),
@@ -74,7 +74,7 @@ def test_tune_with_too_few_steps_keeps_the_shape():
 
 def test_automatic_shape_by_grid_size():
     with btrt.Solver(btrt.problem_from_workload(W.c1(1.0)), W.c1(1.0).phi0()) as s:
-        assert s.launch() == (1, 0, 0, 0)  # 64 x 64: one step per launch
+        assert s.launch() == (1, 4, 0, 0)  # 64 x 64: one step per launch, 64 x 4 tiles
     w = W.c2()
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
         k, rows, group, tile = s.launch()
@@ -84,7 +84,8 @@ def test_automatic_shape_by_grid_size():
 def test_invalid_launch_shapes_are_rejected():
     w = W.c1(1.0)
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
-        for bad in [(5, 0, 0, 0), (-1, 0, 0, 0), (2, -1, 0, 0), (2, 16, 3, 0), (3, 0, 0, 1), (1, 0, 0, 1)]:
+        for bad in [(5, 0, 0, 0), (-1, 0, 0, 0), (2, -1, 0, 0), (2, 16, 3, 0), (3, 0, 0, 1), (1, 0, 0, 1),
+                    (1, 3, 0, 0), (1, 32, 0, 0)]:
             with pytest.raises(btrt.BtrtError) as e:
                 s.set_launch(*bad)
             assert e.value.code == btrt.E_INVAL, bad
