@@ -21,7 +21,7 @@ from paper_1902_09813_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = [("c2", W.c2)]
+CASES = [("c2", W.c2), ("c3", W.c3)]
 
 
 def load(w):
