@@ -69,8 +69,18 @@ static void k1_from_A(const double A[4], double K1[4])
     K1[3] = m[0] / det;
 }
 
+/* The collision of Eq. (6) with the diffusion tensor A0 (1 + beta phi^2) for the given A0. */
+static void collide_with(const orc_problem_t* p, const double A0[3], const double f[9], double phi_prev,
+                         double S, double S_prev, double fpost[9]);
+
 void orc_collide_node(const orc_problem_t* p, const double f[9], double phi_prev,
                       double S, double S_prev, double fpost[9])
+{
+    collide_with(p, p->A0, f, phi_prev, S, S_prev, fpost);
+}
+
+static void collide_with(const orc_problem_t* p, const double A0[3], const double f[9], double phi_prev,
+                         double S, double S_prev, double fpost[9])
 {
     /* Eq. (9): phi is the zeroth moment. */
     double phi = 0.0;
@@ -82,7 +92,7 @@ void orc_collide_node(const orc_problem_t* p, const double f[9], double phi_prev
     /* D = phi I for every problem this project runs. */
     double D[4] = {phi, 0.0, 0.0, phi};
     double g = 1.0 + p->beta * phi * phi;
-    double A[4] = {p->A0[0] * g, p->A0[1] * g, p->A0[1] * g, p->A0[2] * g};
+    double A[4] = {A0[0] * g, A0[1] * g, A0[1] * g, A0[2] * g};
     double K1[4];
     k1_from_A(A, K1);
 
@@ -187,7 +197,7 @@ static void one_step(const orc_problem_t* p, const double* src, double* dst, dou
             for (int i = 0; i < 9; ++i) f[i] = src[i * n + k];
             double s = S ? S[k] : 0.0;
             double sp = S_prev ? S_prev[k] : s;
-            orc_collide_node(p, f, phi_prev[k], s, sp, fp);
+            collide_with(p, p->A0_field ? p->A0_field + 3 * k : p->A0, f, phi_prev[k], s, sp, fp);
 
             /* Eq. (38): f_i(x + c_i, t+1) = f_i^+(x, t); bounce-back at Dirichlet walls. */
             for (int i = 0; i < 9; ++i) {

@@ -39,6 +39,9 @@ typedef struct {
     /* Boundary conditions per side: ORC_PERIODIC or ORC_DIRICHLET with value. */
     int bc_type[4];
     double bc_value[4];
+    /* NULL, or a space-dependent A0(x) (Eq. (73), Eq. (74)): three values (a11, a12, a22)
+     * per node at A0_field[3*(y*nx + x) + j], used in place of A0 by orc_run. */
+    const double* A0_field;
 } orc_problem_t;
 
 /* D2Q9 equilibrium of Eq. (7) for a general D tensor (row major 2x2). */

@@ -43,6 +43,7 @@ class _CProblem(ctypes.Structure):
         ("K2", ctypes.c_double * 4),
         ("bc_type", ctypes.c_int * 4),
         ("bc_value", ctypes.c_double * 4),
+        ("A0_field", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -102,6 +103,7 @@ class Problem:
     K2: Sequence[float] = (1.0, 1.0, 1.0, 1.0)
     bc_type: Sequence[int] = (PERIODIC,) * 4
     bc_value: Sequence[float] = (0.0,) * 4
+    A0_field: Optional[np.ndarray] = None  # (ny, nx, 3): space-dependent A0(x) (Eq. (74))
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -117,6 +119,11 @@ class Problem:
         p.K2[:] = [float(v) for v in K2]
         p.bc_type[:] = [int(v) for v in self.bc_type]
         p.bc_value[:] = [float(v) for v in self.bc_value]
+        if self.A0_field is not None:
+            field = np.ascontiguousarray(self.A0_field, dtype=np.float64)
+            assert field.shape == (self.ny, self.nx, 3)
+            p._field = field  # keeps the array alive as long as the structure
+            p.A0_field = field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         return p
 
 

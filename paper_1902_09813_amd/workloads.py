@@ -27,6 +27,12 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           the requests (seeded coin) use A(phi) = A0 (1 + phi^2); each runs until the Eq. (64)
           residual is <= 1e-8 or 50000 steps; FP32 storage.
 
+* ``c6``  the variable diffusion tensor problem (Eqs. (73)-(76)): unit square, periodic,
+          A(x) = diag(2 - sin(2 pi x) sin(2 pi y), 1) alpha, u = (0.1, 0.1), the source of
+          Eq. (75) = exp((1 - 12 pi^2 alpha) t) S1(x), phi0 = sin(2 pi x) sin(2 pi y), k0 = k2 = 1;
+          N x N cell-centred nodes, dt = dx (lattice speed 1) unless given. In lattice units the
+          source is a field times exp(g n) at step n (g = lambda dt) and A0 is a per-node field.
+
 ``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
 sizes; ragged sizes exercise partial tiles).
 """
@@ -50,7 +56,9 @@ class Workload:
     flux_b: Tuple[float, float] = (0.0, 0.0)
     A0: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     beta: float = 0.0
-    source: Optional[tuple] = None          # None or ("sin", amp, kx, ky)
+    source: Optional[tuple] = None          # None, ("sin", amp, kx, ky) or ("field", S1 (ny, nx), g):
+    #                                         S(x, n) = exp(g n) S1(x) at step n
+    A0_field: Optional[np.ndarray] = None   # (ny, nx, 3) per-node A0 = (a11, a12, a22), or None
     bc_type: Tuple[int, int, int, int] = (PERIODIC,) * 4
     bc_value: Tuple[float, float, float, float] = (0.0,) * 4
     k0: float = 1.0
@@ -80,6 +88,27 @@ def c2() -> Workload:
 def c3() -> Workload:
     return Workload("c3_nonlinear_4096_periodic", 4096, 4096, 5000, flux_b=(0.05, 0.05), A0=(0.01, 0.0, 0.005),
                     beta=1.0, k0=1.0, k2=1.0, seed=3, phi0_kind="gaussians", extra={"count": 16})
+
+
+def c6(alpha: float = 1e-2, n: int = 50, t_end: float = 3.0, u=(0.1, 0.1), dt: Optional[float] = None) -> Workload:
+    """Eqs. (73)-(76) on the unit square with N x N nodes, converted to lattice units."""
+    dx = 1.0 / n
+    dt = dx if dt is None else dt
+    c = np.arange(n, dtype=np.float64) * dx + 0.5 * dx
+    X, Y = np.meshgrid(c, c)
+    sx, sy = np.sin(2 * np.pi * X), np.sin(2 * np.pi * Y)
+    a_lat = alpha * dt / (dx * dx)
+    field = np.zeros((n, n, 3))
+    field[..., 0] = (2.0 - sx * sy) * a_lat
+    field[..., 2] = a_lat
+    # Eq. (75) without its time factor, times dt (the source per lattice step).
+    s1 = (sx * sy + 4.0 * alpha * np.pi ** 2 * np.cos(4 * np.pi * X) * sy ** 2
+          + 2.0 * np.pi * (u[0] * np.cos(2 * np.pi * X) * sy + u[1] * sx * np.cos(2 * np.pi * Y))) * dt
+    lam = 1.0 - 12.0 * np.pi ** 2 * alpha
+    steps = int(round(t_end / dt))
+    return Workload(f"c6_var_tensor_{n}", n, n, steps, flux_a=(u[0] * dt / dx, u[1] * dt / dx),
+                    A0=(0.0, 0.0, 0.0), source=("field", s1, lam * dt), A0_field=field, k0=1.0, k2=1.0,
+                    phi0_kind="sin2", extra={"alpha": alpha, "dt": dt, "dx": dx, "lambda": lam})
 
 
 def initial_field(w: Workload) -> np.ndarray:
@@ -115,6 +144,9 @@ def initial_field(w: Workload) -> np.ndarray:
             dy -= w.ny * np.round(dy / w.ny)
             out += a * np.exp(-(dx * dx + dy * dy) / (2.0 * s * s))
         return out
+    if w.phi0_kind == "sin2":
+        # sin(2 pi x) sin(2 pi y) on the unit square (x = (i + 1/2) / nx).
+        return np.sin(2 * np.pi * X / w.nx) * np.sin(2 * np.pi * Y / w.ny)
     raise ValueError(w.phi0_kind)
 
 

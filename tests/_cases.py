@@ -17,21 +17,43 @@ def oracle_problem(w) -> "O.Problem":
     else:
         k2 = tuple(w.k2)
     return O.Problem(w.nx, w.ny, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta, k0=w.k0, K2=k2,
-                     bc_type=w.bc_type, bc_value=w.bc_value)
+                     bc_type=w.bc_type, bc_value=w.bc_value, A0_field=getattr(w, "A0_field", None))
 
 
 def oracle_source(w):
+    """The time-independent part of the source (the whole source unless it grows in time)."""
     if w.source is None:
         return None
+    if w.source[0] == "field":
+        return np.ascontiguousarray(w.source[1], dtype=np.float64)
     kind, amp, kx, ky = w.source
     assert kind == "sin"
     return O.source_sin(w.nx, w.ny, amp, kx, ky)
 
 
+def source_growth(w) -> float:
+    return float(w.source[2]) if w.source is not None and w.source[0] == "field" else 0.0
+
+
+def advance(o, w, n):
+    """n oracle steps; a source exp(g t) S1(x) is evaluated at every step t, with S(t-1) for
+    Scheme 2 (Remark III) and S(-1) := S(0)."""
+    g = source_growth(w)
+    if g == 0.0:
+        o.step(n)
+        return o
+    base = o.source
+    for _ in range(n):
+        t = o.t
+        S = np.exp(g * t) * base
+        S_prev = np.exp(g * (t - 1)) * base if t > 0 else S
+        o.step(1, S=S, S_prev=S_prev)
+    return o
+
+
 def run_oracle(w, steps=None, nthreads=0) -> "O.Oracle":
     o = O.Oracle(oracle_problem(w), w.phi0(), source=oracle_source(w), nthreads=nthreads)
-    o.step(w.steps if steps is None else steps)
-    return o
+    return advance(o, w, w.steps if steps is None else steps)
 
 
 def normwise(a, ref):
