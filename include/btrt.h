@@ -88,23 +88,31 @@ typedef struct {
     double b[2];
 } btrt_flux_t;
 
-/* A(phi) = [[k11, k12], [k12, k22]] * (1 + beta*phi^2) (Eq. (1)); symmetric positive
- * definite, beta >= 0. Constant when beta == 0. */
+/* A(x, phi) = A0 * (1 + beta*phi^2) (Eq. (1)) with A0 = [[k11, k12], [k12, k22]], or, when
+ * field is not NULL, a space-dependent A0(x) (Eq. (73), Eq. (74)): field[3*(j*nx + i) + q] holds
+ * (a11, a12, a22) of node (i, j), copied at create (k11, k12, k22 are then ignored). Every A0
+ * symmetric positive definite, beta >= 0. K1 (Eq. (30)) is computed per node when beta > 0 or a
+ * field is given. */
 typedef struct {
     double k11, k12, k22;
     double beta;
+    const double* field;
 } btrt_diff_t;
 
 typedef struct {
     int32_t kind; /* BTRT_D_PHI_I */
 } btrt_dterm_t;
 
-/* Source S of Eq. (8), time independent. FIELD: field[j*nx + i], copied at create. */
+/* Source S of Eq. (8): S(x, t) = exp(growth * t) * S0(x) at step t (t = 0, 1, ...), with
+ * S0 = field[j*nx + i] (FIELD, copied at create) or amp*sin(kx pi (i+1/2)/nx)*sin(ky pi
+ * (j+1/2)/ny) (SIN). A source that changes in time enters with the Scheme 2 correction of
+ * Remark III, S(t) + (S(t) - S(t-1))/2, with S(-1) = S(0). growth = 0: time independent. */
 typedef struct {
     int32_t kind; /* BTRT_SRC_NONE, BTRT_SRC_FIELD or BTRT_SRC_SIN */
     double amp;
     int32_t kx, ky;
     const double* field;
+    double growth;
 } btrt_source_t;
 
 /* Sides in the order x-, x+, y-, y+. A periodic side must be paired with its opposite. */
@@ -133,23 +141,24 @@ typedef struct {
     size_t workspace_bytes;           /* device bytes a handle needs */
     double bytes_per_node_launch;     /* algorithmic HBM bytes per node and sweep launch: the
                                          state read once and written once (9 populations +
-                                         phi each way), whether the launch fuses 1 or 2 steps */
+                                         phi each way) plus a source field and an A0 field when
+                                         given, however many steps the launch fuses */
     int64_t step;                     /* steps taken (btrt_get_info only) */
 } btrt_info_t;
 
 /* ---- calls --------------------------------------------------------------------------- */
 
 /* Checks a problem and fills *info (optional) without touching any device.
- * Errors: BTRT_E_INVAL for sizes out of range, unpaired periodic sides, A not SPD or
- * beta < 0, rates outside (0, 2), BTRT_K2_HBB with a non-isotropic or phi-dependent A,
- * an unsupported D or source kind, or non-finite values. */
+ * Errors: BTRT_E_INVAL for sizes out of range, unpaired periodic sides, A (or any node of an
+ * A0 field) not SPD or beta < 0, rates outside (0, 2), BTRT_K2_HBB with a non-isotropic,
+ * phi-dependent or space-dependent A, an unsupported D or source kind, or non-finite values. */
 int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
                   const btrt_dterm_t* D, const btrt_source_t* R, const btrt_bc_t* bc,
                   const btrt_relax_t* relax, btrt_info_t* info);
 
-/* Device bytes btrt_create needs for this grid and source (R may be NULL for no source);
- * 0 when the grid is invalid. */
-size_t btrt_workspace_size(const btrt_grid_t* grid, const btrt_source_t* R);
+/* Device bytes btrt_create needs for this grid, diffusion tensor and source (K and R may be
+ * NULL: constant tensor, no source); 0 when the grid is invalid. */
+size_t btrt_workspace_size(const btrt_grid_t* grid, const btrt_diff_t* K, const btrt_source_t* R);
 
 /* Creates a solver at t = 0 with f = f^eq(phi0) (Section 4: populations start at
  * equilibrium). phi0: nx*ny host values, copied. On success *out owns the device state.
@@ -272,7 +281,8 @@ typedef struct {
  * library creates one). Device memory is allocated by the library (the sum of the instances'
  * btrt_workspace_size plus small tables). Errors: any instance failing btrt_validate or
  * holding a non-finite phi0 -> BTRT_E_INVAL (btrt_last_error names the instance); mixed
- * precisions -> BTRT_E_INVAL; BTRT_E_DEVICE; BTRT_E_NOMEM. Synchronises. */
+ * precisions, an A0 field or a growing source -> BTRT_E_INVAL; BTRT_E_DEVICE; BTRT_E_NOMEM.
+ * Synchronises. */
 int btrt_batch_create(int32_t n, const btrt_problem_t* problems, int32_t device, void* stream,
                       btrt_batch_t** out);
 
@@ -356,8 +366,8 @@ int btrt_server_create(const btrt_server_opts_t* opts, btrt_server_t** out);
 
 /* Queues one request: solve p until the residual is <= tol or max_steps steps (rounded up to
  * whole rounds). p's host arrays are copied. *id receives the request id. Errors: those of
- * btrt_validate, non-finite phi0, a precision other than the server's -> BTRT_E_INVAL; a
- * footprint larger than the server's memory -> BTRT_E_NOMEM. */
+ * btrt_validate, non-finite phi0, a precision other than the server's, an A0 field or a
+ * growing source -> BTRT_E_INVAL; a footprint larger than the server's memory -> BTRT_E_NOMEM. */
 int btrt_server_submit(btrt_server_t* s, const btrt_problem_t* p, double tol, int64_t max_steps, int64_t* id);
 
 /* One scheduling round (see above). Reports resident and queued counts. Synchronises. */

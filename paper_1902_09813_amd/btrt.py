@@ -47,7 +47,7 @@ class Flux(ctypes.Structure):
 
 class Diff(ctypes.Structure):
     _fields_ = [("k11", ctypes.c_double), ("k12", ctypes.c_double), ("k22", ctypes.c_double),
-                ("beta", ctypes.c_double)]
+                ("beta", ctypes.c_double), ("field", ctypes.POINTER(ctypes.c_double))]
 
 
 class DTerm(ctypes.Structure):
@@ -56,7 +56,7 @@ class DTerm(ctypes.Structure):
 
 class Source(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("amp", ctypes.c_double), ("kx", ctypes.c_int32),
-                ("ky", ctypes.c_int32), ("field", ctypes.POINTER(ctypes.c_double))]
+                ("ky", ctypes.c_int32), ("field", ctypes.POINTER(ctypes.c_double)), ("growth", ctypes.c_double)]
 
 
 class BC(ctypes.Structure):
@@ -152,7 +152,7 @@ def lib() -> ctypes.CDLL:
         hp = ctypes.c_void_p
         sig = {
             "btrt_validate": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), P(Info)], ctypes.c_int),
-            "btrt_workspace_size": ([P(Grid), P(Source)], ctypes.c_size_t),
+            "btrt_workspace_size": ([P(Grid), P(Diff), P(Source)], ctypes.c_size_t),
             "btrt_create": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, P(hp)], ctypes.c_int),
             "btrt_step": ([hp, ctypes.c_int64], ctypes.c_int),
             "btrt_set_fusion": ([hp, ctypes.c_int32], ctypes.c_int),
@@ -210,26 +210,35 @@ class Problem:
     """The arguments of btrt_create (Eq. (1) with D = phi I), as ctypes structures.
 
     flux_a, flux_b: B(phi) = a phi + b phi^2/2; A0 = (k11, k12, k22), beta: A = A0 (1 + beta phi^2);
-    source: None, an (ny, nx) array, or ("sin", amp, kx, ky); bc_type/bc_value for sides
-    x-, x+, y-, y+; k0; k2: "hbb" (Eq. (62)), a scalar (K2 = k2 Ihat) or four entries.
+    A0_field: None or an (ny, nx, 3) array of per-node (a11, a12, a22) replacing A0;
+    source: None, an (ny, nx) array, ("sin", amp, kx, ky) or ("field", array, growth) for
+    S(x, t) = exp(growth t) array(x); bc_type/bc_value for sides x-, x+, y-, y+; k0;
+    k2: "hbb" (Eq. (62)), a scalar (K2 = k2 Ihat) or four entries.
     """
 
     def __init__(self, nx: int, ny: int, *, precision: int = F64, flux_a=(0.0, 0.0), flux_b=(0.0, 0.0),
-                 A0=(0.0, 0.0, 0.0), beta: float = 0.0, source=None, bc_type=(PERIODIC,) * 4,
+                 A0=(0.0, 0.0, 0.0), beta: float = 0.0, A0_field=None, source=None, bc_type=(PERIODIC,) * 4,
                  bc_value=(0.0,) * 4, k0: float = 1.0, k2=1.0, check_interval: int = 1000, device: int = 0):
         self.grid = Grid(int(nx), int(ny), int(precision), int(device), None, None, 0)
         self.flux = Flux((ctypes.c_double * 2)(*flux_a), (ctypes.c_double * 2)(*flux_b))
-        self.diff = Diff(float(A0[0]), float(A0[1]), float(A0[2]), float(beta))
+        self._afield = None
+        if A0_field is not None:
+            self._afield = np.ascontiguousarray(A0_field, dtype=np.float64).reshape(ny, nx, 3)
+        self.diff = Diff(float(A0[0]), float(A0[1]), float(A0[2]), float(beta),
+                         _dptr(self._afield) if self._afield is not None else None)
         self.dterm = DTerm(D_PHI_I)
         self._field = None
         if source is None:
-            self.source = Source(SRC_NONE, 0.0, 0, 0, None)
+            self.source = Source(SRC_NONE, 0.0, 0, 0, None, 0.0)
         elif isinstance(source, tuple) and source and source[0] == "sin":
             _, amp, kx, ky = source
-            self.source = Source(SRC_SIN, float(amp), int(kx), int(ky), None)
+            self.source = Source(SRC_SIN, float(amp), int(kx), int(ky), None, 0.0)
         else:
+            growth = 0.0
+            if isinstance(source, tuple) and source and source[0] == "field":
+                _, source, growth = source
             self._field = np.ascontiguousarray(source, dtype=np.float64).reshape(ny, nx)
-            self.source = Source(SRC_FIELD, 0.0, 0, 0, _dptr(self._field))
+            self.source = Source(SRC_FIELD, 0.0, 0, 0, _dptr(self._field), float(growth))
         self.bc = BC((ctypes.c_int32 * 4)(*bc_type), (ctypes.c_double * 4)(*bc_value))
         if isinstance(k2, str):
             assert k2 == "hbb"
@@ -257,7 +266,8 @@ class Problem:
         return info
 
     def workspace_size(self) -> int:
-        return int(lib().btrt_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.source)))
+        return int(lib().btrt_workspace_size(ctypes.byref(self.grid), ctypes.byref(self.diff),
+                                             ctypes.byref(self.source)))
 
 
 class Solver:
@@ -375,8 +385,8 @@ class Solver:
 def problem_from_workload(w, precision: int = F64, device: int = 0, check_interval: int = 1000) -> Problem:
     """btrt_create arguments for a workloads.Workload."""
     return Problem(w.nx, w.ny, precision=precision, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta,
-                   source=w.source, bc_type=w.bc_type, bc_value=w.bc_value, k0=w.k0, k2=w.k2,
-                   check_interval=check_interval, device=device)
+                   A0_field=getattr(w, "A0_field", None), source=w.source, bc_type=w.bc_type,
+                   bc_value=w.bc_value, k0=w.k0, k2=w.k2, check_interval=check_interval, device=device)
 
 
 class Batch:

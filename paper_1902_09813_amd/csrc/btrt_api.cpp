@@ -100,10 +100,10 @@ int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff
     return ok();
 }
 
-size_t btrt_workspace_size(const btrt_grid_t* grid, const btrt_source_t* R)
+size_t btrt_workspace_size(const btrt_grid_t* grid, const btrt_diff_t* K, const btrt_source_t* R)
 {
     if (!grid_ok(grid)) return 0;
-    return layout_for(grid->nx, grid->ny, grid->precision, R ? R->kind : BTRT_SRC_NONE).total;
+    return layout_for(grid->nx, grid->ny, grid->precision, R ? R->kind : BTRT_SRC_NONE, K && K->field).total;
 }
 
 int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
@@ -117,7 +117,7 @@ int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t
     if (rc != BTRT_OK) return rc;
     rc = validate_phi0(grid, phi0);
     if (rc != BTRT_OK) return rc;
-    const size_t need = layout_for(grid->nx, grid->ny, grid->precision, R ? R->kind : BTRT_SRC_NONE).total;
+    const size_t need = layout_for(grid->nx, grid->ny, grid->precision, R ? R->kind : BTRT_SRC_NONE, r.afield).total;
     if (grid->workspace && grid->workspace_bytes < need)
         return fail(BTRT_E_NOMEM, "workspace of %zu bytes < %zu needed", grid->workspace_bytes, need);
 

@@ -60,7 +60,7 @@ int pitch_for(int nx, int precision)
     return (nx + per - 1) / per * per;
 }
 
-Layout layout_for(int nx, int ny, int precision, int src_kind)
+Layout layout_for(int nx, int ny, int precision, int src_kind, bool afield)
 {
     const size_t es = pop_bytes(precision);     // one population value
     const size_t ps = precision == BTRT_F64 ? 8 : 4;  // phi and source values
@@ -89,6 +89,7 @@ Layout layout_for(int nx, int ny, int precision, int src_kind)
         L.src = take(static_cast<size_t>(nx) * ps);
         L.src_y = take(static_cast<size_t>(ny) * ps);
     }
+    L.afield = afield ? take(3 * plane * ps) : 0;
     L.total = off;
     return L;
 }
@@ -116,11 +117,23 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
     if (!grid_ok(grid)) return fail(BTRT_E_INVAL, "grid %d x %d exceeds 2^31 - 1 nodes", grid->nx, grid->ny);
     for (int a = 0; a < 2; ++a)
         if (!is_finite(B->a[a]) || !is_finite(B->b[a])) return fail(BTRT_E_INVAL, "non-finite flux coefficient");
-    if (!is_finite(K->k11) || !is_finite(K->k12) || !is_finite(K->k22) || !is_finite(K->beta))
-        return fail(BTRT_E_INVAL, "non-finite diffusion tensor");
-    if (!(K->k11 > 0.0) || !(K->k22 > 0.0) || !(K->k11 * K->k22 - K->k12 * K->k12 > 0.0))
-        return fail(BTRT_E_INVAL, "diffusion tensor [[%g,%g],[%g,%g]] is not positive definite", K->k11, K->k12,
-                    K->k12, K->k22);
+    if (!is_finite(K->beta)) return fail(BTRT_E_INVAL, "non-finite beta");
+    if (K->field) {
+        // Eq. (73)/(74): every node's A0 must be a finite symmetric positive definite tensor.
+        const int64_t nn = static_cast<int64_t>(grid->nx) * grid->ny;
+        for (int64_t k = 0; k < nn; ++k) {
+            const double a11 = K->field[3 * k], a12 = K->field[3 * k + 1], a22 = K->field[3 * k + 2];
+            if (!is_finite(a11) || !is_finite(a12) || !is_finite(a22) || !(a11 > 0.0) || !(a22 > 0.0) ||
+                !(a11 * a22 - a12 * a12 > 0.0))
+                return fail(BTRT_E_INVAL, "A0 field at node %lld is not a finite SPD tensor", (long long)k);
+        }
+    } else {
+        if (!is_finite(K->k11) || !is_finite(K->k12) || !is_finite(K->k22))
+            return fail(BTRT_E_INVAL, "non-finite diffusion tensor");
+        if (!(K->k11 > 0.0) || !(K->k22 > 0.0) || !(K->k11 * K->k22 - K->k12 * K->k12 > 0.0))
+            return fail(BTRT_E_INVAL, "diffusion tensor [[%g,%g],[%g,%g]] is not positive definite", K->k11, K->k12,
+                        K->k12, K->k22);
+    }
     if (K->beta < 0.0) return fail(BTRT_E_INVAL, "beta = %g < 0", K->beta);
     if (D->kind != BTRT_D_PHI_I) return fail(BTRT_E_INVAL, "D kind %d: only D = phi I is supported", D->kind);
     for (int s = 0; s < 4; ++s) {
@@ -143,12 +156,14 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
         } else if (R->kind != BTRT_SRC_NONE) {
             return fail(BTRT_E_INVAL, "source kind %d", R->kind);
         }
+        if (R->kind != BTRT_SRC_NONE && !is_finite(R->growth)) return fail(BTRT_E_INVAL, "non-finite source growth");
     }
     if (!(relax->k0 > 0.0 && relax->k0 < 2.0)) return fail(BTRT_E_INVAL, "k0 = %g outside (0, 2)", relax->k0);
     if (relax->check_interval < 1) return fail(BTRT_E_INVAL, "check_interval = %d < 1", relax->check_interval);
 
     // K1 from Eq. (30): K1 = (A / c_s^2 + I/2)^-1 with A at phi = 0. For an SPD A its
-    // eigenvalues 1/(3 lambda + 1/2) lie in (0, 2).
+    // eigenvalues 1/(3 lambda + 1/2) lie in (0, 2). (With an A0 field K1 is per node; these
+    // constants are then unused.)
     const double m11 = 3.0 * K->k11 + 0.5, m12 = 3.0 * K->k12, m22 = 3.0 * K->k22 + 0.5;
     const double det = m11 * m22 - m12 * m12;
     res->K1[0] = m22 / det;
@@ -156,12 +171,15 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
     res->K1[2] = -m12 / det;
     res->K1[3] = m11 / det;
     res->k0 = relax->k0;
-    res->k1_per_node = K->beta != 0.0;
+    res->afield = K->field != nullptr;
+    res->k1_per_node = K->beta != 0.0 || res->afield;
+    res->growth = R && R->kind != BTRT_SRC_NONE ? R->growth : 0.0;
 
     if (relax->k2_rule == BTRT_K2_HBB) {
         // Eq. (62) removes the bounce-back slip for K1 = k1 I (Section 3).
-        if (K->k12 != 0.0 || K->k11 != K->k22 || K->beta != 0.0)
-            return fail(BTRT_E_INVAL, "BTRT_K2_HBB needs a constant isotropic A (k11 == k22, k12 == 0, beta == 0)");
+        if (K->field || K->k12 != 0.0 || K->k11 != K->k22 || K->beta != 0.0)
+            return fail(BTRT_E_INVAL,
+                        "BTRT_K2_HBB needs a constant isotropic A (no field, k11 == k22, k12 == 0, beta == 0)");
         const double k1 = res->K1[0];
         const double k2 = 8.0 * (k1 - 2.0) / (3.0 * (k1 - 4.0));
         for (int q = 0; q < 4; ++q) res->K2[q] = k2;
@@ -191,11 +209,13 @@ void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_
         info->K2[q] = r.K2[q];
     }
     info->k0 = r.k0;
-    info->workspace_bytes = layout_for(g->nx, g->ny, g->precision, src_kind).total;
-    // 9 population reads + 9 writes + phi(t-1) read + phi(t) write, plus a per-node source.
+    info->workspace_bytes = layout_for(g->nx, g->ny, g->precision, src_kind, r.afield).total;
+    // 9 population reads + 9 writes + phi(t-1) read + phi(t) write, plus a per-node source and
+    // the three planes of a per-node A0.
     const double es = static_cast<double>(pop_bytes(g->precision));
     const double ps = g->precision == BTRT_F64 ? 8.0 : 4.0;
-    info->bytes_per_node_launch = 18.0 * es + (2.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0)) * ps;
+    info->bytes_per_node_launch =
+        18.0 * es + (2.0 + (src_kind == BTRT_SRC_FIELD ? 1.0 : 0.0) + (r.afield ? 3.0 : 0.0)) * ps;
     info->step = 0;
 }
 
@@ -251,6 +271,8 @@ void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const bt
     a.src_amp = static_cast<T>(R && R->kind == BTRT_SRC_SIN ? R->amp : 0.0);
     a.src = I.kind == kSrcNone ? nullptr : reinterpret_cast<const T*>(I.mem + I.L.src);
     a.src_y = I.kind == kSrcSep ? reinterpret_cast<const T*>(I.mem + I.L.src_y) : nullptr;
+    a.afield = I.afield ? reinterpret_cast<const T*>(I.mem + I.L.afield) : nullptr;
+    for (int l = 0; l < btrtk::kMaxFuse; ++l) a.sfac[l] = T(1);
     // Non-temporal stores once the two buffers of populations and phi exceed the 256 MB
     // Infinity Cache.
     const double state_bytes = 2.0 * static_cast<double>(I.plane) * (9.0 * pop_bytes(I.precision) + sizeof(T));
@@ -273,11 +295,13 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
     I.plane = static_cast<int64_t>(I.pitch) * grid->ny;
     I.kind = src_kind == BTRT_SRC_FIELD ? kSrcField : (src_kind == BTRT_SRC_SIN ? kSrcSep : kSrcNone);
     I.k1_per_node = r.k1_per_node;
+    I.afield = r.afield;
+    I.growth = r.growth;
     I.perx = bc->type[0] == BTRT_PERIODIC;
     I.pery = bc->type[2] == BTRT_PERIODIC;
     for (int q = 0; q < 4; ++q) I.wall[q] = bc->type[q] == BTRT_DIRICHLET ? bc->value[q] : 0.0;
     I.mem = mem;
-    I.L = layout_for(I.nx, I.ny, I.precision, src_kind);
+    I.L = layout_for(I.nx, I.ny, I.precision, src_kind, I.afield);
     I.cur = 0;
     I.step = 0;
     fill_info(grid, r, src_kind, &I.info);
@@ -287,7 +311,7 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
     const size_t nn = static_cast<size_t>(I.nx) * I.ny;
     const size_t es = I.precision == BTRT_F64 ? 8 : 4;  // source values
     double* tmp = reinterpret_cast<double*>(mem + I.L.tmp);
-    hipError_t err;
+    hipError_t err = hipSuccess;
     // Source of Eq. (8): a per-node field, or separable sin tables at cell centres.
     if (src_kind == BTRT_SRC_FIELD) {
         err = hipMemcpyAsync(tmp, R->field, nn * sizeof(double), hipMemcpyHostToDevice, s);
@@ -316,6 +340,21 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         if (err == hipSuccess) err = hipMemcpyAsync(mem + I.L.src_y, py, I.ny * es, hipMemcpyHostToDevice, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) return hip_fail(err, "source table upload");
+    }
+    // Per-node A0(x): three planes (a11, a12, a22) in the phi type.
+    if (I.afield) {
+        std::vector<double> comp(nn);
+        for (int q = 0; q < 3 && err == hipSuccess; ++q) {
+            for (size_t k = 0; k < nn; ++k) comp[k] = K->field[3 * k + q];
+            char* dst = mem + I.L.afield + q * static_cast<size_t>(I.plane) * es;
+            err = hipMemcpyAsync(tmp, comp.data(), nn * sizeof(double), hipMemcpyHostToDevice, s);
+            if (err == hipSuccess)
+                err = I.precision == BTRT_F64
+                          ? launch_convert<double>(tmp, reinterpret_cast<double*>(dst), I.nx, I.ny, I.pitch, s)
+                          : launch_convert<float>(tmp, reinterpret_cast<float*>(dst), I.nx, I.ny, I.pitch, s);
+            if (err == hipSuccess) err = hipStreamSynchronize(s);  // comp and tmp are reused
+        }
+        if (err != hipSuccess) return hip_fail(err, "A0 field upload");
     }
     // 16-bit deviation formats: a power-of-two scale that maps the initial magnitude of phi
     // (and of the wall values) to 2^14, far inside the FP16 range; deviations from
@@ -385,13 +424,37 @@ template SweepArgs<float> sweep_args<float>(const Instance&, int);
 template GatherArgs<double> gather_args<double>(const Instance&);
 template GatherArgs<float> gather_args<float>(const Instance&);
 
+namespace {
+
+// Source factors of the steps a launch advances: S(t) + (S(t) - S(t-1))/2 = S0 (1.5 e(t) -
+// 0.5 e(t-1)) with e(t) = exp(g t) and S(-1) = S(0) (Scheme 2, Remark III); 1 when the source
+// does not change in time. Computed in FP64 on the host, so every launch shape gets the same
+// factors.
+template <typename T>
+SweepArgs<T> with_source_factors(const Instance& I, SweepArgs<T> a, int steps)
+{
+    if (I.growth != 0.0) {
+        for (int l = 0; l < steps && l < btrtk::kMaxFuse; ++l) {
+            const double t = static_cast<double>(I.step + l);
+            const double e = std::exp(I.growth * t);
+            const double ep = t > 0 ? std::exp(I.growth * (t - 1.0)) : e;
+            a.sfac[l] = static_cast<T>(1.5 * e - 0.5 * ep);
+        }
+    }
+    return a;
+}
+
+}  // namespace
+
 int instance_launch(Instance& I, const LaunchCfg& cfg, hipStream_t s)
 {
     hipError_t e;
     if (I.precision == BTRT_F64)
-        e = launch_sweep<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, cfg, s);
+        e = launch_sweep<double>(with_source_factors(I, sweep_args<double>(I, I.cur), cfg.steps), kFmtPlain, I.kind,
+                                 I.kmode(), cfg, s);
     else
-        e = launch_sweep<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, cfg, s);
+        e = launch_sweep<float>(with_source_factors(I, sweep_args<float>(I, I.cur), cfg.steps),
+                                format_of(I.precision), I.kind, I.kmode(), cfg, s);
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     I.cur ^= 1;
     I.step += cfg.steps;
@@ -401,8 +464,8 @@ int instance_launch(Instance& I, const LaunchCfg& cfg, hipStream_t s)
 LaunchCfg instance_resolve(const Instance& I, const LaunchCfg& cfg)
 {
     if (I.precision == BTRT_F64)
-        return resolve_launch<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.k1_per_node, cfg);
-    return resolve_launch<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.k1_per_node, cfg);
+        return resolve_launch<double>(sweep_args<double>(I, I.cur), kFmtPlain, I.kind, I.kmode(), cfg);
+    return resolve_launch<float>(sweep_args<float>(I, I.cur), format_of(I.precision), I.kind, I.kmode(), cfg);
 }
 
 int instance_reduce_async(Instance& I, int mode, hipStream_t s)

@@ -37,9 +37,10 @@ int format_of(int precision);
 
 // Byte offsets of every buffer of one instance inside its memory region.
 struct Layout {
-    size_t f[2], phi[2], snap, tmp, partial, result, src, src_y, total;
+    size_t f[2], phi[2], snap, tmp, partial, result, src, src_y, afield, total;
 };
-Layout layout_for(int nx, int ny, int precision, int src_kind);
+// afield: three planes (a11, a12, a22) of a space-dependent A0(x).
+Layout layout_for(int nx, int ny, int precision, int src_kind, bool afield = false);
 bool grid_ok(const btrt_grid_t* g);
 
 // Constants derived from a validated problem.
@@ -47,7 +48,9 @@ struct Resolved {
     double K1[4];  // Eq. (30) at phi = 0
     double K2[4];  // given, or Eq. (62)
     double k0;
-    bool k1_per_node;
+    bool k1_per_node;  // beta > 0 or a per-node A0(x)
+    bool afield;       // A0(x) given per node
+    double growth;     // source S(x, t) = exp(growth t) S0(x)
 };
 
 int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
@@ -58,10 +61,13 @@ void fill_info(const btrt_grid_t* g, const Resolved& r, int src_kind, btrt_info_
 
 // One problem placed in device memory. State between launches: f+(t-1) in f[cur] and
 // phi(t-1) in phi[cur].
+// K1 mode of the kernels: constant, A0 (1 + beta phi^2), or A0(x) (1 + beta phi^2).
 struct Instance {
     int nx = 0, ny = 0, pitch = 0, precision = 0;
     int kind = 0;         // btrtk::SrcKind of the source
     bool k1_per_node = false;
+    bool afield = false;  // per-node A0(x) planes in the workspace
+    double growth = 0.0;  // source growth rate per step (Scheme 2 correction when nonzero)
     int perx = 1, pery = 1;
     int64_t plane = 0;
     double wall[4] = {0, 0, 0, 0};
@@ -73,6 +79,7 @@ struct Instance {
     SweepArgs<double> a64{};  // problem constants; buffer pointers are set per launch
     SweepArgs<float> a32{};
     btrt_info_t info{};
+    int kmode() const { return afield ? btrtk::kK1Field : (k1_per_node ? btrtk::kK1Phi : btrtk::kK1Const); }
 };
 
 // Places a validated problem into mem (at least layout_for(...).total bytes, 256-byte

@@ -15,6 +15,12 @@ enum SrcKind : int { kSrcNone = 0, kSrcField = 1, kSrcSep = 2 };
 // Reduction modes of the gather kernels.
 enum ReduceMode : int { kResidual = 0, kError = 1 };
 
+// How the kernels obtain K1 (Eq. (30)): the constant of the problem, or per node from
+// A0 (1 + beta phi^2), or per node from a space-dependent A0(x) (1 + beta phi^2).
+enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
+
+constexpr int kMaxFuse = 4;  // most time steps one sweep launch can fuse
+
 // Everything one sweep needs, by value in the kernel argument segment.
 template <typename T>
 struct SweepArgs {
@@ -33,6 +39,8 @@ struct SweepArgs {
     T K11, K12, K22;   // K1 of Eq. (30) when A is constant
     T k0, k2xx, k2xy, k2yy;
     T src_amp;
+    T sfac[kMaxFuse];  // source factor of each step of the launch (1: time independent)
+    const T* afield;   // kK1Field: three planes a11, a12, a22 (plane stride `plane`)
     T dev_scale, dev_inv; // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq)), f+ = f_eq + h dev_inv
     int tiles_x, tiles_y; // set by the launcher for the kernel it picks
     int rows;             // rows per strip of the strip walkers (set by the launcher)
@@ -64,7 +72,6 @@ struct BatchEntry {
     int pad;
 };
 
-constexpr int kMaxFuse = 4;         // most time steps one sweep launch can fuse
 constexpr int kReducePartials = 6; // sum a, sum b, sum c, sum d, max, non-finite count
 constexpr int kReduceBlocks = 1024;
 constexpr int kBlock = 256;
@@ -84,11 +91,11 @@ constexpr int kWalkGroup = 4;
 // levels in registers) or the LDS tile kernel for more; automatic fields of cfg are resolved
 // as resolve_launch does.
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, const LaunchCfg& cfg,
                         hipStream_t s);
 // cfg with its automatic fields filled in for this grid, format and device (the current one).
 template <typename T>
-LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, LaunchCfg cfg);
+LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, LaunchCfg cfg);
 // f+(-1) and phi(-1) := phi0 into a.fin / a.phi_prev (see init_values); FP64 arithmetic.
 template <typename T>
 hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,

@@ -54,10 +54,12 @@ __device__ __forceinline__ void store(T* p, T v, bool nontemporal)
 }
 
 template <typename T, int SRC>
-__device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int y)
+// Source term of step `lvl` of the launch at node n = (x, y): the time-independent part times
+// that step's factor (Scheme 2 folded in, 1 for a source constant in time).
+__device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int y, int lvl)
 {
-    if constexpr (SRC == kSrcField) return a.src[n];
-    if constexpr (SRC == kSrcSep) return a.src_amp * a.src[x] * a.src_y[y];
+    if constexpr (SRC == kSrcField) return a.src[n] * a.sfac[lvl];
+    if constexpr (SRC == kSrcSep) return (a.src_amp * a.src[x] * a.src_y[y]) * a.sfac[lvl];
     return T(0);
 }
 
@@ -172,7 +174,7 @@ struct Dev {
 // ---- one time step --------------------------------------------------------------------------
 
 // One time step on tile (tx, ty) of kTileX x rows nodes, one node per thread.
-template <typename F, int SRC, bool KPHI>
+template <typename F, int SRC, int KM>
 __device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx, int ty, int rows)
 {
     using T = typename F::T;
@@ -182,18 +184,18 @@ __device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx,
     T f[9];
     F::pull(a, x, y, f);
     const int n = y * a.pitch + x;
-    const T phi = collide<T, SRC, KPHI>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y));
+    const T phi = collide<T, SRC, KM>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y, 0), n);
     F::put(a, n, f, phi);
 }
 
 // Tiles of 64 x (blockDim.x / 64) nodes; taller tiles re-read fewer halo rows of their
 // neighbours above and below.
-template <typename F, int SRC, bool KPHI>
+template <typename F, int SRC, int KM>
 __global__ __launch_bounds__(kMaxBlock1) void sweep_kernel(SweepArgs<typename F::T> a)
 {
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
-    tile1<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, static_cast<int>(blockDim.x) / kTileX);
+    tile1<F, SRC, KM>(a, tile - ty * a.tiles_x, ty, static_cast<int>(blockDim.x) / kTileX);
 }
 
 // Wrap a coordinate of a periodic direction into [0, n) (any distance).
@@ -220,7 +222,7 @@ struct Tile2 {
     static constexpr int S2 = (kTile2X * TY + kBlock2 - 1) / kBlock2;
 };
 
-template <typename F, int SRC, bool KPHI>
+template <typename F, int SRC, int KM>
 __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx, int ty,
                                       typename F::T (&lf)[9][Tile2<typename F::T>::E],
                                       typename F::T (&lphi)[Tile2<typename F::T>::E])
@@ -261,7 +263,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         if (!live[j]) continue;
         const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
         const int n = gys[j] * a.pitch + gxs[j];
-        const T phi = collide<T, SRC, KPHI>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j]));
+        const T phi = collide<T, SRC, KM>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j], 0), n);
         F::settle(a, f[j], phi);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lf[i][s] = f[j][i];
@@ -292,12 +294,12 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
         g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
         const int n = gy * a.pitch + gx;
-        const T phi = collide<T, SRC, KPHI>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy));
+        const T phi = collide<T, SRC, KM>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy, 1), n);
         F::put(a, n, g, phi);
     }
 }
 
-template <typename F, int SRC, bool KPHI>
+template <typename F, int SRC, int KM>
 __global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<typename F::T> a)
 {
     using T = typename F::T;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(kBlock2) void sweep2_kernel(SweepArgs<typename F::T
     __shared__ T lphi[Tile2<T>::E];
     const int tile = xcd_tile();
     const int ty = tile / a.tiles_x;
-    tile2<F, SRC, KPHI>(a, tile - ty * a.tiles_x, ty, lf, lphi);
+    tile2<F, SRC, KM>(a, tile - ty * a.tiles_x, ty, lf, lphi);
 }
 
 // ---- K time steps per launch: strip walkers ------------------------------------------------
@@ -398,10 +400,10 @@ __device__ __forceinline__ WalkRow walk_row(int q, int ny, int pery)
 // Level l >= 2 at one node: pull from level l-1's rows below (up: populations 2, 5, 6), at
 // (mid) and above (fresh, just produced), then collide. All lanes must be active here (the
 // wavefront shifts read the neighbouring lanes).
-template <typename T, int SRC, bool KPHI, bool WALLS>
+template <typename T, int SRC, int KM, bool WALLS>
 __device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], const Level<T>& mid,
                                           const Level<T>& fresh, int x, bool okxm, bool okxp, const WalkRow& row,
-                                          T g[9])
+                                          int lvl, T g[9])
 {
     const T* m = mid.f;
     const T s1 = lane_shift<kShr1>(m[1]);
@@ -425,7 +427,7 @@ __device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], 
     g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
     g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
     const int n = row.y * a.pitch + x;
-    return collide<T, SRC, KPHI>(a, g, mid.phi, source_at<T, SRC>(a, n, x, row.y));
+    return collide<T, SRC, KM>(a, g, mid.phi, source_at<T, SRC>(a, n, x, row.y, lvl), n);
 }
 
 // Level-1 inputs of row r at column x, as raw loads: for each direction the source address is
@@ -526,7 +528,7 @@ constexpr int kAhead = sizeof(T) == 8 ? 1 : 2;
 // One row of the walk: level 1 on row r, levels 2..K on rows r-1 .. r-(K-1). PH picks which
 // of the two row buffers per level is current; the next call uses the other. `in` holds the
 // loads of row r and receives those of row r + kAhead.
-template <typename F, int SRC, bool KPHI, int K, bool WALLS, int PH>
+template <typename F, int SRC, int KM, int K, bool WALLS, int PH>
 __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, const WalkLane& L, int r, int r1,
                                           WalkIn<F>& in, WalkState<typename F::T, K>& st)
 {
@@ -539,7 +541,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
     {
         const WalkRow w = walk_row(r, a.ny, a.pery);
         const int n = w.y * a.pitch + L.x;
-        const T phi = collide<T, SRC, KPHI>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y));
+        const T phi = collide<T, SRC, KM>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y, 0), n);
         F::settle(a, lev.f, phi);
         lev.phi = phi;
         // Keep level 1 (and so the wait for its loads) ahead of the stores below.
@@ -564,7 +566,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
         T g[9];
         T phi = T(0);
         if (q >= L.ys - (K - l)) {
-            phi = walk_collide<T, SRC, KPHI, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, g);
+            phi = walk_collide<T, SRC, KM, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, l - 1, g);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = T(0);
@@ -590,7 +592,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
 // A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
 // in one band of rows; they walk in lockstep (one barrier per row, no memory fence: they share
 // no data), so the rows they read and write at a time are contiguous across the group.
-template <typename F, int SRC, bool KPHI, int K, bool WALLS>
+template <typename F, int SRC, int KM, int K, bool WALLS>
 __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typename F::T> a)
 {
     using T = typename F::T;
@@ -640,8 +642,8 @@ __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typen
     walk_load<F, WALLS>(a, L.x, L.colok, r0, in[0]);
     if (kAhead<T> == 2 && r0 + 1 < r1) walk_load<F, WALLS>(a, L.x, L.colok, r0 + 1, in[kAhead<T> - 1]);
     for (int r = r0; r < r1; r += 2) {
-        walk_step<F, SRC, KPHI, K, WALLS, 0>(a, L, r, r1, in[0], st);
-        if (r + 1 < r1) walk_step<F, SRC, KPHI, K, WALLS, 1>(a, L, r + 1, r1, in[kAhead<T> - 1], st);
+        walk_step<F, SRC, KM, K, WALLS, 0>(a, L, r, r1, in[0], st);
+        if (r + 1 < r1) walk_step<F, SRC, KM, K, WALLS, 1>(a, L, r + 1, r1, in[kAhead<T> - 1], st);
     }
     if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
 }
@@ -677,12 +679,12 @@ __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __r
         const int tiles_x = (a.nx + kTileX - 1) / kTileX;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile1<F, kSrcNone, false>(a, tx, ty, kTileY); break;
-            case 1: tile1<F, kSrcNone, true>(a, tx, ty, kTileY); break;
-            case 2: tile1<F, kSrcField, false>(a, tx, ty, kTileY); break;
-            case 3: tile1<F, kSrcField, true>(a, tx, ty, kTileY); break;
-            case 4: tile1<F, kSrcSep, false>(a, tx, ty, kTileY); break;
-            default: tile1<F, kSrcSep, true>(a, tx, ty, kTileY); break;
+            case 0: tile1<F, kSrcNone, kK1Const>(a, tx, ty, kTileY); break;
+            case 1: tile1<F, kSrcNone, kK1Phi>(a, tx, ty, kTileY); break;
+            case 2: tile1<F, kSrcField, kK1Const>(a, tx, ty, kTileY); break;
+            case 3: tile1<F, kSrcField, kK1Phi>(a, tx, ty, kTileY); break;
+            case 4: tile1<F, kSrcSep, kK1Const>(a, tx, ty, kTileY); break;
+            default: tile1<F, kSrcSep, kK1Phi>(a, tx, ty, kTileY); break;
         }
     }
 }
@@ -703,12 +705,12 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
         const int tiles_x = (a.nx + kTile2X - 1) / kTile2X;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile2<F, kSrcNone, false>(a, tx, ty, lf, lphi); break;
-            case 1: tile2<F, kSrcNone, true>(a, tx, ty, lf, lphi); break;
-            case 2: tile2<F, kSrcField, false>(a, tx, ty, lf, lphi); break;
-            case 3: tile2<F, kSrcField, true>(a, tx, ty, lf, lphi); break;
-            case 4: tile2<F, kSrcSep, false>(a, tx, ty, lf, lphi); break;
-            default: tile2<F, kSrcSep, true>(a, tx, ty, lf, lphi); break;
+            case 0: tile2<F, kSrcNone, kK1Const>(a, tx, ty, lf, lphi); break;
+            case 1: tile2<F, kSrcNone, kK1Phi>(a, tx, ty, lf, lphi); break;
+            case 2: tile2<F, kSrcField, kK1Const>(a, tx, ty, lf, lphi); break;
+            case 3: tile2<F, kSrcField, kK1Phi>(a, tx, ty, lf, lphi); break;
+            case 4: tile2<F, kSrcSep, kK1Const>(a, tx, ty, lf, lphi); break;
+            default: tile2<F, kSrcSep, kK1Phi>(a, tx, ty, lf, lphi); break;
         }
         __syncthreads();  // the next tile reuses the LDS
     }
@@ -866,7 +868,7 @@ int device_cus()
 }
 
 // Resident wavefronts per CU of one walker instantiation (its registers decide).
-template <typename F, int SRC, bool KP, int K>
+template <typename F, int SRC, int KP, int K>
 int walk_waves_per_cu()
 {
     static const int waves = [] {
@@ -885,7 +887,7 @@ int walk_waves_per_cu()
 //  - strip rows: the largest of 32, 16, 8 that still gives every resident wavefront slot about
 //    two strips (rows at least 8);
 //  - strips per group: kWalkGroup with 32-row strips (large grids), else 1.
-template <typename F, int SRC, bool KP, int K>
+template <typename F, int SRC, int KP, int K>
 void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
 {
     constexpr int W = Walk<K>::W;
@@ -903,7 +905,7 @@ void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
     if (cfg.group <= 0) cfg.group = cfg.rows >= 32 ? kWalkGroup : 1;
 }
 
-template <typename F, int SRC, bool KP>
+template <typename F, int SRC, int KP>
 LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
 {
     if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kMaxFuse : 1;
@@ -925,7 +927,7 @@ LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
     return cfg;
 }
 
-template <typename F, int SRC, bool KP, int K>
+template <typename F, int SRC, int KP, int K>
 hipError_t walk_launch(SweepArgs<typename F::T> a, const LaunchCfg& cfg, hipStream_t s)
 {
     constexpr int W = Walk<K>::W;
@@ -941,7 +943,7 @@ hipError_t walk_launch(SweepArgs<typename F::T> a, const LaunchCfg& cfg, hipStre
     return hipGetLastError();
 }
 
-template <typename F, int SRC, bool KP>
+template <typename F, int SRC, int KP>
 hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t s)
 {
     using T = typename F::T;
@@ -971,33 +973,35 @@ hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t 
     }
 }
 
-// Source kind x per-node K1 dispatch of FN<F, SRC, KP>(args...).
-#define BTRT_BY_VARIANT(FN, ...)                                                   \
-    do {                                                                           \
-        if (k1_per_node) {                                                         \
-            if (src_kind == kSrcField) return FN<F, kSrcField, true>(__VA_ARGS__); \
-            if (src_kind == kSrcSep) return FN<F, kSrcSep, true>(__VA_ARGS__);     \
-            return FN<F, kSrcNone, true>(__VA_ARGS__);                             \
-        }                                                                          \
-        if (src_kind == kSrcField) return FN<F, kSrcField, false>(__VA_ARGS__);    \
-        if (src_kind == kSrcSep) return FN<F, kSrcSep, false>(__VA_ARGS__);        \
-        return FN<F, kSrcNone, false>(__VA_ARGS__);                                \
+// Source kind x K1 mode dispatch of FN<F, SRC, KM>(args...).
+#define BTRT_BY_SRC(KMV, FN, ...)                                                \
+    do {                                                                         \
+        if (src_kind == kSrcField) return FN<F, kSrcField, KMV>(__VA_ARGS__);    \
+        if (src_kind == kSrcSep) return FN<F, kSrcSep, KMV>(__VA_ARGS__);        \
+        return FN<F, kSrcNone, KMV>(__VA_ARGS__);                                \
+    } while (0)
+#define BTRT_BY_VARIANT(FN, ...)                                                 \
+    do {                                                                         \
+        if (kmode == kK1Field) BTRT_BY_SRC(kK1Field, FN, __VA_ARGS__);           \
+        if (kmode == kK1Phi) BTRT_BY_SRC(kK1Phi, FN, __VA_ARGS__);               \
+        BTRT_BY_SRC(kK1Const, FN, __VA_ARGS__);                                  \
     } while (0)
 
 template <typename F>
-hipError_t sweep_with(const SweepArgs<typename F::T>& a, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+hipError_t sweep_with(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg,
                       hipStream_t s)
 {
     BTRT_BY_VARIANT(sweep_variant, a, cfg, s);
 }
 
 template <typename F>
-LaunchCfg resolve_with(const SweepArgs<typename F::T>& a, int src_kind, bool k1_per_node, const LaunchCfg& cfg)
+LaunchCfg resolve_with(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg)
 {
     BTRT_BY_VARIANT(resolve_variant, a, cfg);
 }
 
 #undef BTRT_BY_VARIANT
+#undef BTRT_BY_SRC
 
 template <typename F>
 hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], double ax, double ay,
@@ -1048,21 +1052,21 @@ hipError_t reduce_with(const GatherArgs<typename F::T>& a, int mode, double* res
     } while (0)
 
 template <typename T>
-hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, const LaunchCfg& cfg,
+hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, const LaunchCfg& cfg,
                         hipStream_t s)
 {
-    BTRT_BY_FORMAT(T, sweep_with, a, src_kind, k1_per_node, cfg, s);
+    BTRT_BY_FORMAT(T, sweep_with, a, src_kind, kmode, cfg, s);
 }
 
 template <typename T>
-LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, bool k1_per_node, LaunchCfg cfg)
+LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, LaunchCfg cfg)
 {
     if constexpr (sizeof(T) == 8) {
-        return resolve_with<Plain<T>>(a, src_kind, k1_per_node, cfg);
+        return resolve_with<Plain<T>>(a, src_kind, kmode, cfg);
     } else {
-        if (fmt == kFmtF16Dev) return resolve_with<Dev<F16Codec>>(a, src_kind, k1_per_node, cfg);
-        if (fmt == kFmtBF16Dev) return resolve_with<Dev<BF16Codec>>(a, src_kind, k1_per_node, cfg);
-        return resolve_with<Plain<T>>(a, src_kind, k1_per_node, cfg);
+        if (fmt == kFmtF16Dev) return resolve_with<Dev<F16Codec>>(a, src_kind, kmode, cfg);
+        if (fmt == kFmtBF16Dev) return resolve_with<Dev<BF16Codec>>(a, src_kind, kmode, cfg);
+        return resolve_with<Plain<T>>(a, src_kind, kmode, cfg);
     }
 }
 
@@ -1115,8 +1119,8 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
 }
 
 #define BTRT_INSTANTIATE(T)                                                                                        \
-    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, bool, const LaunchCfg&, hipStream_t);      \
-    template LaunchCfg resolve_launch<T>(const SweepArgs<T>&, int, int, bool, LaunchCfg);                        \
+    template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, int, const LaunchCfg&, hipStream_t);       \
+    template LaunchCfg resolve_launch<T>(const SweepArgs<T>&, int, int, int, LaunchCfg);                         \
     template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], double, double,   \
                                        double, double, hipStream_t);                                               \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, int, hipStream_t);                           \

@@ -117,8 +117,10 @@ __host__ __device__ inline T sum9(const T f[9])
 // f+(x, t) on return. Returns phi(t). The library is built without floating-point
 // contraction: every fused multiply-add below is written out, so a node update rounds the
 // same way in every kernel that inlines it.
-template <typename T, int SRC, bool KPHI>
-__host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, T s)
+// KM (K1Mode) selects where K1 comes from; n is the node's in-plane index (read only for an
+// A0 field). s is the source term of the step, with the Scheme 2 correction folded in.
+template <typename T, int SRC, int KM>
+__host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, T s, int n)
 {
     constexpr T third = T(1) / T(3);
     constexpr T sixth = T(1) / T(6);
@@ -146,13 +148,20 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     const T dBx = fmadd(-phi_prev, fmadd(hbx, phi_prev, a.ax), Bx);
     const T dBy = fmadd(-phi_prev, fmadd(hby, phi_prev, a.ay), By);
 
-    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)), per node when A depends on phi.
+    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)), per node when A depends on phi or on x
+    // (A = A0(x) (1 + beta phi^2), Eq. (73)).
     T K11 = a.K11, K12 = a.K12, K22 = a.K22;
-    if constexpr (KPHI) {
+    if constexpr (KM != kK1Const) {
+        T a11 = a.a11, a12 = a.a12, a22 = a.a22;
+        if constexpr (KM == kK1Field) {
+            a11 = a.afield[n];
+            a12 = a.afield[a.plane + n];
+            a22 = a.afield[2 * a.plane + n];
+        }
         const T g = fmadd(a.beta, phi * phi, T(1));
-        const T m11 = fmadd(T(3) * a.a11, g, half);
-        const T m12 = (T(3) * a.a12) * g;
-        const T m22 = fmadd(T(3) * a.a22, g, half);
+        const T m11 = fmadd(T(3) * a11, g, half);
+        const T m12 = (T(3) * a12) * g;
+        const T m22 = fmadd(T(3) * a22, g, half);
         const T rdet = T(1) / fmadd(m11, m22, -(m12 * m12));
         K11 = m22 * rdet;
         K12 = -m12 * rdet;

@@ -100,3 +100,22 @@ def test_bytes_and_workspace():
     assert btrt.Problem(100, 3, A0=(0.01, 0, 0.01)).validate().pitch == 128
     assert btrt.Problem(100, 3, precision=btrt.F32, A0=(0.01, 0, 0.01)).validate().pitch == 128
     assert btrt.Problem(65, 3, A0=(0.01, 0, 0.01)).validate().pitch == 96
+
+
+def test_space_dependent_tensor_and_growing_source_reach_the_library():
+    # The A0 field and the source growth travel through the structures: a non-SPD node is
+    # named, the field adds three planes to the workspace and to the bytes per launch, and
+    # batches refuse both (checked on the host, before any device work).
+    w = W.c6(1e-3, 16)
+    p = btrt.problem_from_workload(w)
+    info = p.validate()
+    assert info.k1_per_node == 1
+    assert info.bytes_per_node_launch == (18 + 2 + 1 + 3) * 8  # plus the source field and A0(x)
+    plain = btrt.Problem(16, 16, A0=(0.01, 0.0, 0.01), source=w.source[1])
+    assert p.workspace_size() - plain.workspace_size() >= 3 * 16 * 16 * 8
+    bad = w.A0_field.copy()
+    bad[3, 5, 1] = 1.0  # a12^2 > a11 a22 at node (5, 3)
+    msg = _expect_inval(btrt.Problem(16, 16, A0_field=bad, source=w.source))
+    assert "node 53" in msg
+    _expect_inval(btrt.Problem(16, 16, A0_field=w.A0_field, k2="hbb"))
+    _expect_inval(btrt.Problem(16, 16, A0=(0.01, 0.0, 0.01), source=("field", w.source[1], np.inf)))
