@@ -28,12 +28,18 @@ HBM_PEAK_GBS = 8000.0
 CHECK_INTERVAL = 1000
 METRIC = "MLUPS and % HBM roofline, batched/served vs plain; p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_09813_amd", "csrc", "btrt_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1902_09813_amd", "csrc")
+KERNEL_SOURCES = ("btrt_internal.h", "btrt_node.h", "btrt_device.h", "btrt_sweep_f64.hip", "btrt_sweep_f32.hip",
+                  "btrt_sweep_f16dev.hip", "btrt_sweep_bf16dev.hip", "btrt_batch_kernels.hip", "btrt_kernels.hip")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256 (first 16 hex digits) over the device-code sources, in a fixed order."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def sweep_launches(steps, fusion):
@@ -115,7 +121,7 @@ def timed_run(w, precision, steps, warmup, fusion=0, launch=None):
     }
 
 
-def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=400):
+def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=1200):
     """The 256 uneven FP32 instances: one batched launch per fused step (tuned) against a loop
     of plain per-instance launches on one stream. Returns MLUPS of both."""
     import torch
@@ -138,7 +144,8 @@ def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=400):
         torch.cuda.synchronize()
         ms = a.elapsed_time(e)
         out["batched_mlups"] = round(nodes * (steps - used) / (ms * 1e-3) / 1e6, 1)
-        out["batched_config"] = {"steps_per_launch": best[0], "blocks_per_cu": best[1], "graph_launches": best[2]}
+        out["batched_config"] = {"steps_per_launch": best[0], "blocks_per_cu": best[1], "graph_launches": best[2],
+                                 "strip_rows": best[3]}
     with torch.cuda.stream(stream):
         solvers = [btrt.Solver(btrt.problem_from_workload(w, precision=btrt.F32), ph, torch_memory=True)
                    for w, (_, ph) in zip(ws, probs)]
@@ -159,7 +166,7 @@ def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=400):
     return out
 
 
-def served(duration_s=20.0, calib_requests=12, seed=5):
+def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 0, 0)):
     """Served solves: Poisson arrivals of FP32 requests (side 64..2048, residual <= 1e-8 or
     50000 steps) into the continuous-batching server. The arrival rate is 0.8 x the rate the
     server sustains on a backlog (calibration run). Time to solution is measured from each
@@ -170,17 +177,19 @@ def served(duration_s=20.0, calib_requests=12, seed=5):
 
     stream = torch.cuda.Stream()
     opts = dict(precision=btrt.F32, memory_bytes=48 << 30, max_active=128, check_interval=1000,
-                launch=(2, 0, 0), stream=stream.cuda_stream)
-    # Calibration: a backlog of requests submitted at once.
-    calib = W.c5(calib_requests, rate=1.0, seed=seed + 7)
-    with btrt.Server(**opts) as srv:
-        ids = [srv.submit(btrt.problem_from_workload(w, precision=btrt.F32), w.phi0(), tol, ms)
-               for _, w, tol, ms in calib]
-        t0 = srv.clock()
-        while any(srv.info(i)["status"] < btrt.REQ_DONE for i in ids):
-            srv.pump()
-        sustain = calib_requests / (srv.clock() - t0)
-    rate = 0.8 * sustain
+                launch=launch, stream=stream.cuda_stream)
+    sustain = None
+    if rate is None:
+        # Calibration: a backlog of requests submitted at once.
+        calib = W.c5(calib_requests, rate=1.0, seed=seed + 7)
+        with btrt.Server(**opts) as srv:
+            ids = [srv.submit(btrt.problem_from_workload(w, precision=btrt.F32), w.phi0(), tol, ms)
+                   for _, w, tol, ms in calib]
+            t0 = srv.clock()
+            while any(srv.info(i)["status"] < btrt.REQ_DONE for i in ids):
+                srv.pump()
+            sustain = calib_requests / (srv.clock() - t0)
+        rate = 0.8 * sustain
     n_req = max(4, int(rate * duration_s))
     reqs = W.c5(n_req, rate=rate, seed=seed)
     lat, done_ids = [], []
@@ -208,7 +217,8 @@ def served(duration_s=20.0, calib_requests=12, seed=5):
     return {
         "requests": n_req,
         "rate_per_s": round(rate, 3),
-        "sustained_rate_per_s": round(sustain, 3),
+        "sustained_rate_per_s": round(sustain, 3) if sustain else None,
+        "launch": list(launch),
         "p50_s": round(float(np.percentile(lat, 50)), 3),
         "p99_s": round(float(np.percentile(lat, 99)), 3),
         "mean_steps": round(float(np.mean(steps)), 1),

@@ -268,13 +268,17 @@ typedef struct {
     const double* phi0;
 } btrt_problem_t;
 
-/* How a batch launches: time steps fused per launch (1 or 2), resident blocks per compute
- * unit of the persistent grid (0: one block per tile), and launches captured per HIP graph
- * replay (0: no graph; otherwise even, >= 2). */
+/* How a batch launches: time steps fused per launch (1: 64 x 4 tiles; 2: the two-step LDS
+ * tiles; 4: strip walkers, one wavefront per strip of 58 columns by strip_rows rows), resident
+ * blocks per compute unit of the persistent grid (0: one block per tile or strip; with 4 steps
+ * four one-wavefront blocks per unit), launches captured per HIP graph replay (0: no graph;
+ * otherwise even, >= 2), and the walkers' strip height (0: 16; at most 4096). Every
+ * configuration gives the same bits. */
 typedef struct {
     int32_t steps_per_launch;
     int32_t blocks_per_cu;
     int32_t graph_launches;
+    int32_t strip_rows;
 } btrt_batch_config_t;
 
 /* Creates a batch of n >= 1 instances at t = 0 on `device`, enqueuing on `stream` (NULL: the
@@ -303,8 +307,10 @@ int btrt_batch_get_config(const btrt_batch_t* b, btrt_batch_config_t* cfg);
 
 /* Autotuner: times each candidate configuration on the batch itself by running steps of the
  * solve (every configuration computes the same bits, so these steps count as ordinary
- * steps), at most max_steps in total; keeps and reports the fastest. *steps_used = steps
- * taken. Synchronises. */
+ * steps), at most max_steps in total; keeps and reports the fastest. Candidates: 4 steps per
+ * launch with 16- and 32-row strips, 2 and 1 steps, each with 0 or 4 blocks per CU and with
+ * or without 16-launch graphs, 4 warm-up and a multiple of 64 timed steps each (none when
+ * max_steps < 16 * 68). *steps_used = steps taken. Synchronises. */
 int btrt_batch_tune(btrt_batch_t* b, int64_t max_steps, btrt_batch_config_t* best, int64_t* steps_used);
 
 /* Steps taken so far. */
@@ -340,7 +346,9 @@ typedef struct {
     size_t memory_bytes;        /* device memory reserved for resident requests */
     int32_t max_active;         /* resident requests at most (>= 1) */
     int32_t check_interval;     /* steps per round; the residual is checked after each round */
-    btrt_batch_config_t launch; /* launch configuration of the batched sweeps */
+    btrt_batch_config_t launch; /* launch configuration of the batched sweeps; steps_per_launch
+                                   0: chosen per round (two-step tiles below 2^21 resident nodes,
+                                   four-step walkers with 16-row strips from there on) */
 } btrt_server_opts_t;
 
 typedef struct {

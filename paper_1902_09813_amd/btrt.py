@@ -90,10 +90,10 @@ class Launch(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("steps_per_launch", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("graph_launches", ctypes.c_int32)]
+                ("graph_launches", ctypes.c_int32), ("strip_rows", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.steps_per_launch, self.blocks_per_cu, self.graph_launches)
+        return (self.steps_per_launch, self.blocks_per_cu, self.graph_launches, self.strip_rows)
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
@@ -419,8 +419,9 @@ class Batch:
         _check(lib().btrt_batch_residual(self.h, _dptr(out)), "btrt_batch_residual")
         return out
 
-    def set_config(self, steps_per_launch: int = 2, blocks_per_cu: int = 0, graph_launches: int = 0) -> "Batch":
-        c = BatchConfig(int(steps_per_launch), int(blocks_per_cu), int(graph_launches))
+    def set_config(self, steps_per_launch: int = 2, blocks_per_cu: int = 0, graph_launches: int = 0,
+                   strip_rows: int = 0) -> "Batch":
+        c = BatchConfig(int(steps_per_launch), int(blocks_per_cu), int(graph_launches), int(strip_rows))
         _check(lib().btrt_batch_set_config(self.h, ctypes.byref(c)), "btrt_batch_set_config")
         return self
 
@@ -466,7 +467,7 @@ class Server:
     ``pump`` runs one scheduling round."""
 
     def __init__(self, precision: int = F32, memory_bytes: int = 8 << 30, max_active: int = 64,
-                 check_interval: int = 1000, launch=(2, 0, 0), device: int = 0, stream: Optional[int] = None):
+                 check_interval: int = 1000, launch=(0, 0, 0, 0), device: int = 0, stream: Optional[int] = None):
         o = ServerOpts(int(precision), int(device), stream, int(memory_bytes), int(max_active), int(check_interval),
                        BatchConfig(*[int(v) for v in launch]))
         h = ctypes.c_void_p()

@@ -1,0 +1,41 @@
+// Launchers of the batched kernels (one persistent launch over the tiles or strips of every
+// instance of a batch or server round).
+
+#include "btrt_device.h"
+
+namespace btrtk {
+
+template <typename T>
+hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
+                              int flip, int steps, int grid, int rows, hipStream_t s)
+{
+    if (total_tiles <= 0 || ninst <= 0) return hipSuccess;
+    if (steps == kBatchWalkK) {
+        // Several resident strips per CU: a persistent grid of `grid` blocks covers the list.
+        const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid * kWalkGroup, total_tiles) : total_tiles);
+        hipLaunchKernelGGL((batchw_kernel<T>), dim3(g), dim3(kWave), 0, s, ent, begin, par, ninst, total_tiles, flip,
+                           rows);
+        return hipGetLastError();
+    }
+    const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid, total_tiles) : total_tiles);
+    if (steps == 2)
+        hipLaunchKernelGGL((batch2_kernel<T>), dim3(g), dim3(kBlock2), 0, s, ent, begin, par, ninst, total_tiles, flip);
+    else
+        hipLaunchKernelGGL((batch1_kernel<T>), dim3(g), dim3(kBlock), 0, s, ent, begin, par, ninst, total_tiles, flip);
+    return hipGetLastError();
+}
+
+int batch_strip_columns() { return Walk<kBatchWalkK>::W; }
+
+int tile_rows(int steps, int precision_bytes)
+{
+    if (steps == 2) return precision_bytes == 8 ? Tile2<double>::TY : Tile2<float>::TY;
+    return kTileY;
+}
+
+template hipError_t launch_batch_sweep<double>(const BatchEntry<double>*, const int*, const int*, int, int, int, int,
+                                               int, int, hipStream_t);
+template hipError_t launch_batch_sweep<float>(const BatchEntry<float>*, const int*, const int*, int, int, int, int,
+                                              int, int, hipStream_t);
+
+}  // namespace btrtk

@@ -31,14 +31,51 @@ void drop_graph(Group& g)
 
 int grid_blocks(const Group& g) { return g.cfg.blocks_per_cu > 0 ? g.ncu * g.cfg.blocks_per_cu : 0; }
 
+constexpr int kDefaultStripRows = 16;
+int strip_rows(const btrt_batch_config_t& c) { return c.strip_rows > 0 ? c.strip_rows : kDefaultStripRows; }
+
 hipError_t raw_launch(Group& g, int steps, int flip)
 {
     const int n = static_cast<int>(g.inst.size());
+    const int rows = strip_rows(g.cfg);
     if (g.precision == BTRT_F64)
         return btrtk::launch_batch_sweep<double>(static_cast<const BatchEntry<double>*>(g.d_ent), g.d_begin[steps],
-                                                 g.d_par, n, g.total[steps], flip, steps, grid_blocks(g), g.stream);
+                                                 g.d_par, n, g.total[steps], flip, steps, grid_blocks(g), rows,
+                                                 g.stream);
     return btrtk::launch_batch_sweep<float>(static_cast<const BatchEntry<float>*>(g.d_ent), g.d_begin[steps], g.d_par,
-                                            n, g.total[steps], flip, steps, grid_blocks(g), g.stream);
+                                            n, g.total[steps], flip, steps, grid_blocks(g), rows, g.stream);
+}
+
+// Offsets of each member's units in the concatenated list for `steps` per launch: 64 x rows
+// tiles (1 and 2 steps), or strips of the 4-step walker (batch_strip_columns() x rows).
+int upload_begin(Group& g, int steps, int rows)
+{
+    const int n = static_cast<int>(g.inst.size());
+    std::vector<int> begin(n + 1);
+    const int width = steps == 4 ? btrtk::batch_strip_columns() : btrtk::kTileWidth;
+    int64_t acc = 0;
+    for (int i = 0; i < n; ++i) {
+        begin[i] = static_cast<int>(acc);
+        const Instance& I = *g.inst[i];
+        acc += static_cast<int64_t>((I.nx + width - 1) / width) * ((I.ny + rows - 1) / rows);
+    }
+    if (acc > INT32_MAX) return fail(BTRT_E_INVAL, "more than 2^31 - 1 tiles in one group");
+    begin[n] = static_cast<int>(acc);
+    g.total[steps] = static_cast<int>(acc);
+    hipError_t e = hipMemcpyAsync(g.d_begin[steps], begin.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice,
+                                  g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "group table upload");
+}
+
+// The 4-step strip table for the configured strip height (built when first needed).
+int ensure_walk_table(Group& g)
+{
+    const int rows = strip_rows(g.cfg);
+    if (g.walk_rows == rows || g.inst.empty()) return BTRT_OK;
+    int rc = upload_begin(g, 4, rows);
+    if (rc == BTRT_OK) g.walk_rows = rows;
+    return rc;
 }
 
 void advance(Group& g, int steps, int launches)
@@ -97,7 +134,8 @@ void fill_entries(const Group& g, std::vector<BatchEntry<T>>& ent, bool nts)
 
 bool config_ok(const btrt_batch_config_t* c)
 {
-    return c && (c->steps_per_launch == 1 || c->steps_per_launch == 2) && c->blocks_per_cu >= 0 &&
+    return c && (c->steps_per_launch == 1 || c->steps_per_launch == 2 || c->steps_per_launch == 4) &&
+           c->strip_rows >= 0 && c->strip_rows <= 4096 && c->blocks_per_cu >= 0 &&
            c->blocks_per_cu <= 64 && c->graph_launches >= 0 && c->graph_launches <= 4096 &&
            (c->graph_launches == 0 || (c->graph_launches >= 2 && c->graph_launches % 2 == 0));
 }
@@ -112,7 +150,7 @@ int group_init(Group& g, int device, hipStream_t s, int precision, int capacity)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         g.ncu = prop.multiProcessorCount;
     const size_t bytes = align_up(capacity * entry_bytes(precision)) +
-                         3 * align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
+                         4 * align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
     if (hipMalloc(reinterpret_cast<void**>(&g.tables), bytes) != hipSuccess) {
         g.tables = nullptr;
         (void)hipGetLastError();
@@ -124,6 +162,8 @@ int group_init(Group& g, int device, hipStream_t s, int precision, int capacity)
     g.d_begin[1] = reinterpret_cast<int*>(t);
     t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
     g.d_begin[2] = reinterpret_cast<int*>(t);
+    t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
+    g.d_begin[4] = reinterpret_cast<int*>(t);
     t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
     g.d_par = reinterpret_cast<int*>(t);
     if (hipHostMalloc(reinterpret_cast<void**>(&g.h_res),
@@ -140,25 +180,16 @@ int group_upload(Group& g)
     const int n = static_cast<int>(g.inst.size());
     if (n > g.capacity) return fail(BTRT_E_INVAL, "group of %d exceeds its capacity %d", n, g.capacity);
     g.flip = 0;
+    g.walk_rows = 0;
     if (n == 0) {
-        g.total[1] = g.total[2] = 0;
+        g.total[1] = g.total[2] = g.total[4] = 0;
         return BTRT_OK;
     }
-    std::vector<int> begin(n + 1), par(n);
+    std::vector<int> par(n);
     hipError_t e = hipSuccess;
-    for (int steps = 1; steps <= 2 && e == hipSuccess; ++steps) {
-        const int rows = btrtk::tile_rows(steps, g.precision == BTRT_F64 ? 8 : 4);
-        int64_t acc = 0;
-        for (int i = 0; i < n; ++i) {
-            begin[i] = static_cast<int>(acc);
-            const Instance& I = *g.inst[i];
-            acc += static_cast<int64_t>((I.nx + btrtk::kTileWidth - 1) / btrtk::kTileWidth) * ((I.ny + rows - 1) / rows);
-        }
-        if (acc > INT32_MAX) return fail(BTRT_E_INVAL, "more than 2^31 - 1 tiles in one group");
-        begin[n] = static_cast<int>(acc);
-        g.total[steps] = static_cast<int>(acc);
-        e = hipMemcpyAsync(g.d_begin[steps], begin.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, g.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    for (int steps = 1; steps <= 2; ++steps) {
+        int rc = upload_begin(g, steps, btrtk::tile_rows(steps, g.precision == BTRT_F64 ? 8 : 4));
+        if (rc != BTRT_OK) return rc;
     }
     for (int i = 0; i < n; ++i) par[i] = g.inst[i]->cur;
     if (e == hipSuccess)
@@ -186,6 +217,10 @@ int group_upload(Group& g)
 int group_enqueue(Group& g, int64_t n)
 {
     if (g.inst.empty()) return BTRT_OK;
+    if (g.cfg.steps_per_launch == 4) {
+        int rc = ensure_walk_table(g);
+        if (rc != BTRT_OK) return rc;
+    }
     const int k = g.cfg.steps_per_launch;
     const int L = g.cfg.graph_launches;
     int64_t left = n;
@@ -198,7 +233,8 @@ int group_enqueue(Group& g, int64_t n)
                 left -= k;
             }
             if (!g.gexec || g.gcfg.steps_per_launch != g.cfg.steps_per_launch ||
-                g.gcfg.blocks_per_cu != g.cfg.blocks_per_cu || g.gcfg.graph_launches != L) {
+                g.gcfg.blocks_per_cu != g.cfg.blocks_per_cu || g.gcfg.graph_launches != L ||
+                strip_rows(g.gcfg) != strip_rows(g.cfg)) {
                 int rc = build_graph(g);
                 if (rc != BTRT_OK) return rc;
             }
@@ -211,7 +247,8 @@ int group_enqueue(Group& g, int64_t n)
         }
     }
     while (left > 0) {
-        const int s = (k == 2 && left >= 2) ? 2 : 1;
+        // Whole launches of k steps, then 2 and 1 for the remainder.
+        const int s = left >= k ? k : (left >= 2 ? 2 : 1);
         int rc = launch_once(g, s);
         if (rc != BTRT_OK) return rc;
         left -= s;
@@ -246,11 +283,15 @@ int group_residuals(Group& g, double* out, int* bad)
 int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* used_out)
 {
     std::vector<btrt_batch_config_t> cand;
+    for (int rows : {16, 32})
+        for (int bpc : {0, 4})
+            for (int gl : {0, 16}) cand.push_back({4, bpc, gl, rows});
     for (int steps : {2, 1})
-        for (int bpc : {0, 2, 4, 8})
-            for (int gl : {0, 16}) cand.push_back({steps, bpc, gl});
-    // Each candidate: four warm-up steps, then a timed run of a multiple of 32 steps.
-    const int64_t per = std::max<int64_t>(0, max_steps / static_cast<int64_t>(cand.size()) - 4) / 32 * 32;
+        for (int bpc : {0, 4})
+            for (int gl : {0, 16}) cand.push_back({steps, bpc, gl, 0});
+    // Each candidate: four warm-up steps, then a timed run of a multiple of 64 steps (one graph
+    // replay of 16 four-step launches).
+    const int64_t per = std::max<int64_t>(0, max_steps / static_cast<int64_t>(cand.size()) - 4) / 64 * 64;
     const btrt_batch_config_t keep = g.cfg;
     int64_t used = 0;
     double best_ms = INFINITY;

@@ -117,16 +117,17 @@ struct Group {
     int ncu = 256;
     int capacity = 0;
     std::vector<Instance*> inst;
-    char* tables = nullptr;  // device: entries, tile offsets (1- and 2-step tiles), parities
+    char* tables = nullptr;  // device: entries, tile offsets (1- and 2-step tiles, 4-step strips), parities
     void* d_ent = nullptr;
-    int* d_begin[3] = {nullptr, nullptr, nullptr};
+    int* d_begin[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // indexed by steps per launch
     int* d_par = nullptr;
-    int total[3] = {0, 0, 0};
-    int flip = 0;  // launches since group_upload, mod 2
-    btrt_batch_config_t cfg{2, 0, 0};
+    int total[5] = {0, 0, 0, 0, 0};
+    int walk_rows = 0;  // strip height the 4-step table was built for (0: not built)
+    int flip = 0;       // launches since group_upload, mod 2
+    btrt_batch_config_t cfg{2, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    btrt_batch_config_t gcfg{0, 0, 0};
+    btrt_batch_config_t gcfg{0, 0, 0, 0};
     double* h_res = nullptr;  // pinned, capacity * kReducePartials
 };
 

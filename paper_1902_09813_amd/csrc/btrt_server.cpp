@@ -97,6 +97,10 @@ struct Request {
 
 }  // namespace
 
+// Resident nodes from which an automatic launch configuration uses the strip walkers (measured
+// on gfx950 with the served workload: below it the rounds are latency-bound).
+constexpr int64_t kAutoWalkNodes = int64_t(1) << 21;
+
 struct btrt_server {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -113,6 +117,7 @@ struct btrt_server {
     std::deque<int64_t> queue;
     std::vector<int64_t> active;
     bool dirty = false;  // membership changed since the group tables were written
+    bool auto_launch = false;  // choose the launch configuration per round from the resident work
     btrt_server_stats_t st{};
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -187,7 +192,7 @@ int btrt_server_create(const btrt_server_opts_t* o, btrt_server_t** out)
     if (!out) return fail(BTRT_E_INVAL, "out is NULL");
     *out = nullptr;
     if (!o || (o->precision != BTRT_F64 && o->precision != BTRT_F32) || o->max_active < 1 || o->check_interval < 1 ||
-        o->memory_bytes < kAlign || !config_ok(&o->launch))
+        o->memory_bytes < kAlign || (o->launch.steps_per_launch != 0 && !config_ok(&o->launch)))
         return fail(BTRT_E_INVAL, "invalid server options");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -222,7 +227,8 @@ int btrt_server_create(const btrt_server_opts_t* o, btrt_server_t** out)
         release(s);
         return fail(rc, "%s", msg.c_str());
     }
-    s->group.cfg = o->launch;
+    s->auto_launch = o->launch.steps_per_launch == 0;
+    if (!s->auto_launch) s->group.cfg = o->launch;
     s->arena.reset(s->mem_bytes);
     *out = s;
     return ok();
@@ -285,6 +291,14 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued)
         s->dirty = false;
     }
     if (rc == BTRT_OK && !s->active.empty()) {
+        if (s->auto_launch) {
+            // Few resident nodes: the rounds are latency-bound and the fully parallel two-step
+            // tiles finish them sooner; from kAutoWalkNodes on, four-step strip walkers (16-row
+            // strips) move the state once per four steps. Every configuration gives the same bits.
+            int64_t nodes = 0;
+            for (int64_t id : s->active) nodes += static_cast<int64_t>(s->req[id]->inst.nx) * s->req[id]->inst.ny;
+            s->group.cfg = nodes >= kAutoWalkNodes ? btrt_batch_config_t{4, 0, 0, 16} : btrt_batch_config_t{2, 0, 0, 0};
+        }
         rc = group_enqueue(s->group, s->check_interval);
         std::vector<double> res(s->active.size());
         int bad = 0;

@@ -1,0 +1,18 @@
+// Sweep kernels of the FP32 populations storage format (all source kinds, K1 modes and launch
+// shapes), instantiated in this translation unit alone.
+
+#include "btrt_device.h"
+
+namespace btrtk {
+
+hipError_t sweep_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s)
+{
+    return sweep_with<Plain<float>>(a, src_kind, kmode, cfg, s);
+}
+
+LaunchCfg resolve_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg)
+{
+    return resolve_with<Plain<float>>(a, src_kind, kmode, cfg);
+}
+
+}  // namespace btrtk

@@ -128,3 +128,35 @@ def test_fp64_served_result_matches_oracle():
         for rid, (p, ph, tol, ms, w) in zip(ids, reqs):
             w.steps = 600
             assert normwise(srv.result(rid), run_oracle(w).phi()) <= 1e-12, w.name
+
+
+@pytest.mark.parametrize("launch", [(4, 0, 0, 16), (4, 2, 0, 32), (1, 0, 0, 0)], ids=["walk16", "walk32_b2", "one_step"])
+def test_server_launch_configurations_match_single_handle(launch):
+    reqs = requests(5, seed=17, max_steps=1200, tol=0.0)
+    with btrt.Server(precision=btrt.F32, check_interval=200, max_active=8, launch=launch) as srv:
+        ids = [srv.submit(*r[:4]) for r in reqs]
+        drain(srv, ids)
+        for rid, (p, ph, tol, ms, w) in zip(ids, reqs):
+            with btrt.Solver(btrt.problem_from_workload(w, precision=btrt.F32, check_interval=200), ph) as s:
+                steps, res = s.solve(tol, ms)
+                assert steps == srv.info(rid)["steps"]
+                assert np.array_equal(s.field(), srv.result(rid)), (launch, w.name)
+
+
+def test_automatic_launch_switches_with_the_resident_work():
+    # Two large requests (together above 2^21 nodes) make the server switch to the strip walkers
+    # while both are resident and back once one retires; the bits stay those of a single handle.
+    big = [W.c5(1, rate=1.0, seed=s_, side_range=(1100, 1101), tol=0.0, max_steps=ms_)[0][1]
+           for s_, ms_ in ((51, 600), (52, 1400))]
+    small = requests(3, seed=53, max_steps=1000, tol=0.0)
+    with btrt.Server(precision=btrt.F32, check_interval=200, max_active=8) as srv:
+        jobs = [(srv.submit(btrt.problem_from_workload(w, precision=btrt.F32, check_interval=200), w.phi0(), 0.0,
+                            w.steps), w) for w in big]
+        jobs += [(srv.submit(*r[:4]), r[4]) for r in small]
+        drain(srv, [j for j, _ in jobs])
+        for rid, w in jobs:
+            info = srv.info(rid)
+            assert info["status"] == btrt.REQ_DONE
+            with btrt.Solver(btrt.problem_from_workload(w, precision=btrt.F32, check_interval=200), w.phi0()) as s:
+                s.step(info["steps"])
+                assert np.array_equal(s.field(), srv.result(rid)), w.name
