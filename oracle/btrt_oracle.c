@@ -18,6 +18,7 @@
  */
 #include "btrt_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -35,10 +36,20 @@ static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 /* c_s^2 = c^2/3 with c = 1. */
 static const double CS2 = 1.0 / 3.0;
 
-/* B(phi) = a*phi + b*phi^2/2 (the flux families the library accepts). */
+/* B(phi) = a*phi + b*phi^2/2 + c*|phi|^q (the flux families the library accepts). */
 static void flux(const orc_problem_t* p, double phi, double B[2])
 {
-    for (int a = 0; a < 2; ++a) B[a] = p->flux_a[a] * phi + p->flux_b[a] * phi * phi / 2.0;
+    for (int a = 0; a < 2; ++a) {
+        B[a] = p->flux_a[a] * phi + p->flux_b[a] * phi * phi / 2.0;
+        if (p->flux_c[a] != 0.0) B[a] += p->flux_c[a] * pow(fabs(phi), p->flux_q);
+    }
+}
+
+/* The phi-dependent part of S(x, phi, t) in Eq. (1): r phi (1 - |phi|^p). */
+static double reaction(const orc_problem_t* p, double phi)
+{
+    if (p->src_r == 0.0) return 0.0;
+    return p->src_r * phi * (1.0 - pow(fabs(phi), p->src_p));
 }
 
 void orc_equilibrium(double phi, const double B[2], const double D[4], double feq[9])
@@ -89,6 +100,9 @@ static void collide_with(const orc_problem_t* p, const double A0[3], const doubl
     double B[2], Bp[2];
     flux(p, phi, B);
     flux(p, phi_prev, Bp);
+    /* S(x, phi, t): the given part plus the phi-dependent one, at t and at t-1 (Scheme 2). */
+    S += reaction(p, phi);
+    S_prev += reaction(p, phi_prev);
     /* D = phi I for every problem this project runs. */
     double D[4] = {phi, 0.0, 0.0, phi};
     double g = 1.0 + p->beta * phi * phi;

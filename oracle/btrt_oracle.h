@@ -42,6 +42,16 @@ typedef struct {
     /* NULL, or a space-dependent A0(x) (Eq. (73), Eq. (74)): three values (a11, a12, a22)
      * per node at A0_field[3*(y*nx + x) + j], used in place of A0 by orc_run. */
     const double* A0_field;
+    /* Power-law part of the flux: B(phi) gains flux_c * |phi|^flux_q per component (the
+     * convection a phi^delta d_x phi of Eq. (67) is the divergence of a phi^(delta+1)/(delta+1)
+     * along x). Ignored when both flux_c are 0. */
+    double flux_c[2];
+    double flux_q;
+    /* Source depending on phi (Eq. (1), S(x, phi, t)): r phi (1 - |phi|^p) is added to the
+     * given S, at phi(t) for S(t) and at phi(t-1) for S(t-1) (the reaction term of Eq. (67)
+     * with r = b, p = delta). Ignored when src_r is 0. */
+    double src_r;
+    double src_p;
 } orc_problem_t;
 
 /* D2Q9 equilibrium of Eq. (7) for a general D tensor (row major 2x2). */
@@ -49,7 +59,9 @@ void orc_equilibrium(double phi, const double B[2], const double D[4], double fe
 
 /* One node collision of Eq. (6): f -> f+, with the correction G of Eq. (11)
  * (time derivative of B as a backward difference over one step), the source
- * of Eq. (8) and its time derivative by Scheme 2 (Remark III). */
+ * of Eq. (8) and its time derivative by Scheme 2 (Remark III). S and S_prev are
+ * the parts of the source that do not depend on phi; the phi-dependent part of
+ * the problem is added at phi = sum f and at phi_prev. */
 void orc_collide_node(const orc_problem_t* p, const double f[9], double phi_prev,
                       double S, double S_prev, double fpost[9]);
 

@@ -12,6 +12,8 @@ solutions used as pins:
 * ``residual``             Eq. (64), relative L1 change used as the steady criterion.
 * ``gaussian_hill``        Eq. (71), the anisotropic Gaussian hill (with periodic images).
 * ``source_sin``           the separable sinusoidal source of the benchmark problems.
+* ``burgers_fisher``       Eqs. (68)-(69), the travelling wave of the Burgers-Fisher equation.
+* ``WallLinks``            per-link Dirichlet values from values along each side.
 
 Nothing here imports the product package.
 """
@@ -44,6 +46,10 @@ class _CProblem(ctypes.Structure):
         ("bc_type", ctypes.c_int * 4),
         ("bc_value", ctypes.c_double * 4),
         ("A0_field", ctypes.POINTER(ctypes.c_double)),
+        ("flux_c", ctypes.c_double * 2),
+        ("flux_q", ctypes.c_double),
+        ("src_r", ctypes.c_double),
+        ("src_p", ctypes.c_double),
     ]
 
 
@@ -87,10 +93,11 @@ def _ptr(a: Optional[np.ndarray]):
 class Problem:
     """One B-TriRT problem in lattice units (Eq. (1) with D = phi I).
 
-    flux:   B(phi) = a phi + b phi^2 / 2 per component.
+    flux:   B(phi) = a phi + b phi^2 / 2 + c |phi|^q per component.
     A0, beta: A(phi) = A0 (1 + beta phi^2), A0 = (a11, a12, a22) symmetric.
     k0, K2: relaxation of the S0 block and the 2x2 K2 block of Eq. (6) (row major).
     bc_type/bc_value: sides x-, x+, y-, y+.
+    src_r, src_p: phi-dependent source r phi (1 - |phi|^p), added to any given S.
     """
 
     nx: int
@@ -104,6 +111,10 @@ class Problem:
     bc_type: Sequence[int] = (PERIODIC,) * 4
     bc_value: Sequence[float] = (0.0,) * 4
     A0_field: Optional[np.ndarray] = None  # (ny, nx, 3): space-dependent A0(x) (Eq. (74))
+    flux_c: Sequence[float] = (0.0, 0.0)
+    flux_q: float = 1.0
+    src_r: float = 0.0
+    src_p: float = 1.0
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -119,6 +130,10 @@ class Problem:
         p.K2[:] = [float(v) for v in K2]
         p.bc_type[:] = [int(v) for v in self.bc_type]
         p.bc_value[:] = [float(v) for v in self.bc_value]
+        p.flux_c[:] = [float(v) for v in self.flux_c]
+        p.flux_q = float(self.flux_q)
+        p.src_r = float(self.src_r)
+        p.src_p = float(self.src_p)
         if self.A0_field is not None:
             field = np.ascontiguousarray(self.A0_field, dtype=np.float64)
             assert field.shape == (self.ny, self.nx, 3)
@@ -260,3 +275,59 @@ def gaussian_hill(nx: int, ny: int, t: float, x0: Sequence[float], sigma0: float
             q = si[0, 0] * dx * dx + (si[0, 1] + si[1, 0]) * dx * dy + si[1, 1] * dy * dy
             out += np.exp(-0.5 * q)
     return pref * out
+
+
+def burgers_fisher(X, Y, t: float, a: float, alpha: float, b: float, delta: float) -> np.ndarray:
+    """Eqs. (68)-(69): {1/2 + tanh[A (x + y - omega t)] / 2}^(1/delta) with
+    A = -a delta / (4 alpha (delta + 1)) and omega = a / (delta + 1) + 2 b alpha (delta + 1) / a.
+
+    The speed printed with Eq. (69) has (delta + 1) where this one has (delta + 1)^2 in the
+    b alpha term; substituting the wave into Eq. (67) (where the diffusion acts along x + y with
+    coefficient 2 alpha) leaves a residual unless the square is there, so the square is read
+    as intended."""
+    A = -a * delta / (4.0 * alpha * (delta + 1.0))
+    omega = a / (delta + 1.0) + 2.0 * b * alpha * (delta + 1.0) / a
+    return (0.5 + 0.5 * np.tanh(A * (np.asarray(X) + np.asarray(Y) - omega * t))) ** (1.0 / delta)
+
+
+class WallLinks:
+    """Per-link Dirichlet values (9, ny, nx) for orc_run from values along the sides.
+
+    The sides are given as one vector v of 2 (nx + ny) values: x- at rows j (v[j]), x+ at
+    rows j (v[ny + j]), y- at columns i (v[2 ny + i]), y+ at columns i (v[2 ny + nx + i]).
+    A link of node (i, j) leaving through side x- or x+ takes that side's value at row j,
+    through y- or y+ the value at column i, and a diagonal link leaving through a corner point
+    the mean of the two (Eqs. (54)-(56) with a wall value that varies along the side).
+    """
+
+    CX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
+    CY = (0, 0, 1, 0, -1, 1, 1, -1, -1)
+
+    def __init__(self, nx: int, ny: int, bc_type: Sequence[int]):
+        self.nx, self.ny = nx, ny
+        perx, pery = bc_type[0] == PERIODIC, bc_type[2] == PERIODIC
+        links, ia, ib = [], [], []
+        edge = sorted({(i, j) for j in range(ny) for i in (0, nx - 1)}
+                      | {(i, j) for i in range(nx) for j in (0, ny - 1)}, key=lambda q: (q[1], q[0]))
+        for k in range(1, 9):
+            for i, j in edge:
+                outx = not perx and not (0 <= i + self.CX[k] < nx)
+                outy = not pery and not (0 <= j + self.CY[k] < ny)
+                if not (outx or outy):
+                    continue
+                vx = (j if self.CX[k] < 0 else ny + j) if outx else -1
+                vy = (2 * ny + i if self.CY[k] < 0 else 2 * ny + nx + i) if outy else -1
+                links.append((k * ny + j) * nx + i)
+                ia.append(vx if outx else vy)
+                ib.append(vy if outy else vx)
+        self.links = np.asarray(links, dtype=np.int64)
+        self.ia = np.asarray(ia, dtype=np.int64)
+        self.ib = np.asarray(ib, dtype=np.int64)
+        self.out = np.zeros((9, ny, nx))
+
+    def __call__(self, v: np.ndarray) -> np.ndarray:
+        v = np.asarray(v, dtype=np.float64)
+        assert v.shape == (2 * (self.nx + self.ny),)
+        flat = self.out.reshape(-1)
+        flat[self.links] = 0.5 * (v[self.ia] + v[self.ib])
+        return self.out

@@ -33,13 +33,20 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           N x N cell-centred nodes, dt = dx (lattice speed 1) unless given. In lattice units the
           source is a field times exp(g n) at step n (g = lambda dt) and A0 is a per-node field.
 
+* ``bfe``  the Burgers-Fisher equation (Eqs. (67)-(69)) on [-1, 2]^2 with N nodes per unit
+          length (3N x 3N cell-centred nodes), lattice speed c (dt = dx / c), a = 2, b = 0.05,
+          delta = 1.5 unless given: in lattice units B(phi) = (a / ((delta + 1) c)) |phi|^(delta+1)
+          along x, A = alpha dt / dx^2 I, S(phi) = b dt phi (1 - |phi|^delta), k0 = 1, k2 from
+          Eq. (62); phi0 and the Dirichlet values on all four walls from Eq. (68), the walls at
+          time (k + 1) dt for the k-th step.
+
 ``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
 sizes; ragged sizes exercise partial tiles).
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
-from typing import Optional, Tuple
+from typing import Callable, Optional, Tuple
 
 import numpy as np
 
@@ -66,6 +73,12 @@ class Workload:
     seed: int = 0
     phi0_kind: str = "uniform"
     extra: dict = field(default_factory=dict)
+    flux_c: Tuple[float, float] = (0.0, 0.0)  # B(phi) gains c |phi|^q
+    flux_q: float = 1.0
+    src_r: float = 0.0                      # S gains r phi (1 - |phi|^p)
+    src_p: float = 1.0
+    walls: Optional[Callable[[int], np.ndarray]] = None  # k -> Dirichlet values of the k-th step
+    #                                         along the sides: x- (ny), x+ (ny), y- (nx), y+ (nx)
 
     def phi0(self) -> np.ndarray:
         return initial_field(self)
@@ -111,6 +124,43 @@ def c6(alpha: float = 1e-2, n: int = 50, t_end: float = 3.0, u=(0.1, 0.1), dt: O
                     phi0_kind="sin2", extra={"alpha": alpha, "dt": dt, "dx": dx, "lambda": lam})
 
 
+def _bfe_wave(x, y, t, a, alpha, b, delta):
+    """The travelling wave of Eqs. (68)-(69) (boundary and initial data of the bfe workload), with
+    the speed a / (delta + 1) + 2 b alpha (delta + 1) / a that makes it solve Eq. (67) in 2-D."""
+    k = -a * delta / (4.0 * alpha * (delta + 1.0))
+    speed = (a * a + 2.0 * b * alpha * (delta + 1.0) ** 2) / (a * (delta + 1.0))
+    return (0.5 + 0.5 * np.tanh(k * (x + y - speed * t))) ** (1.0 / delta)
+
+
+def bfe(n: int = 40, alpha: float = 0.05, a: float = 2.0, b: float = 0.05, delta: float = 1.5, c: float = 5.0,
+        t_end: float = 1.0) -> Workload:
+    """The Burgers-Fisher problem on [-1, 2]^2 (Eqs. (67)-(69)), n nodes per unit length."""
+    dx = 1.0 / n
+    dt = dx / c
+    m = 3 * n
+    centres = -1.0 + (np.arange(m, dtype=np.float64) + 0.5) * dx
+    steps = int(round(t_end / dt))
+    a_lat = alpha * dt / (dx * dx)
+
+    def walls(k: int) -> np.ndarray:
+        t = (k + 1) * dt
+        lo, hi = np.full(m, -1.0), np.full(m, 2.0)
+        return np.concatenate([_bfe_wave(lo, centres, t, a, alpha, b, delta),
+                               _bfe_wave(hi, centres, t, a, alpha, b, delta),
+                               _bfe_wave(centres, lo, t, a, alpha, b, delta),
+                               _bfe_wave(centres, hi, t, a, alpha, b, delta)])
+
+    bc0 = walls(-1)
+    return Workload(f"bfe_a{a:g}_alpha{alpha:g}_{m}", m, m, steps, A0=(a_lat, 0.0, a_lat),
+                    bc_type=(DIRICHLET,) * 4, bc_value=(float(bc0[0]), float(bc0[m]), float(bc0[2 * m]),
+                                                        float(bc0[3 * m])),
+                    k0=1.0, k2="hbb", phi0_kind="bfe",
+                    flux_c=(a / ((delta + 1.0) * c), 0.0), flux_q=delta + 1.0, src_r=b * dt, src_p=delta,
+                    walls=walls,
+                    extra={"a": a, "alpha": alpha, "b": b, "delta": delta, "c": c, "dx": dx, "dt": dt,
+                           "x0": -1.0})
+
+
 def initial_field(w: Workload) -> np.ndarray:
     """phi0 on the cell-centred nodes (i + 1/2, j + 1/2), shape (ny, nx)."""
     x = np.arange(w.nx, dtype=np.float64) + 0.5
@@ -144,6 +194,11 @@ def initial_field(w: Workload) -> np.ndarray:
             dy -= w.ny * np.round(dy / w.ny)
             out += a * np.exp(-(dx * dx + dy * dy) / (2.0 * s * s))
         return out
+    if w.phi0_kind == "bfe":
+        e = w.extra
+        c = e["x0"] + (np.arange(w.nx, dtype=np.float64) + 0.5) * e["dx"]
+        Xp, Yp = np.meshgrid(c, c)
+        return _bfe_wave(Xp, Yp, 0.0, e["a"], e["alpha"], e["b"], e["delta"])
     if w.phi0_kind == "sin2":
         # sin(2 pi x) sin(2 pi y) on the unit square (x = (i + 1/2) / nx).
         return np.sin(2 * np.pi * X / w.nx) * np.sin(2 * np.pi * Y / w.ny)

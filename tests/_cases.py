@@ -17,7 +17,8 @@ def oracle_problem(w) -> "O.Problem":
     else:
         k2 = tuple(w.k2)
     return O.Problem(w.nx, w.ny, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta, k0=w.k0, K2=k2,
-                     bc_type=w.bc_type, bc_value=w.bc_value, A0_field=getattr(w, "A0_field", None))
+                     bc_type=w.bc_type, bc_value=w.bc_value, A0_field=getattr(w, "A0_field", None),
+                     flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p)
 
 
 def oracle_source(w):
@@ -37,17 +38,26 @@ def source_growth(w) -> float:
 
 def advance(o, w, n):
     """n oracle steps; a source exp(g t) S1(x) is evaluated at every step t, with S(t-1) for
-    Scheme 2 (Remark III) and S(-1) := S(0)."""
+    Scheme 2 (Remark III) and S(-1) := S(0); Dirichlet values that change in time are taken
+    from the workload's schedule at every step."""
     g = source_growth(w)
-    if g == 0.0:
+    if g == 0.0 and w.walls is None:
         o.step(n)
         return o
     base = o.source
+    links = None
+    if w.walls is not None:
+        links = getattr(o, "_wall_links", None)
+        if links is None:
+            links = o._wall_links = O.WallLinks(w.nx, w.ny, w.bc_type)
     for _ in range(n):
         t = o.t
-        S = np.exp(g * t) * base
-        S_prev = np.exp(g * (t - 1)) * base if t > 0 else S
-        o.step(1, S=S, S_prev=S_prev)
+        S = S_prev = None
+        if g != 0.0:
+            S = np.exp(g * t) * base
+            S_prev = np.exp(g * (t - 1)) * base if t > 0 else S
+        wall = links(w.walls(t)) if links is not None else None
+        o.step(1, S=S, S_prev=S_prev, wall=wall)
     return o
 
 
