@@ -4,7 +4,7 @@
  * convection-diffusion equations (Zhao, Wu, Chai & Shi, arXiv:1902.09813).
  *
  * The library solves Eq. (1),
- *     d_t phi + div B(phi) = div[ A(phi) grad . D(phi) ] + S(x),
+ *     d_t phi + div B(phi) = div[ A(x, phi) grad . D(phi) ] + S(x, phi, t),
  * in lattice units (dx = dt = 1, c = 1, c_s^2 = 1/3), with the evolution equation
  * Eq. (6) (equivalently its moment form, Eq. (94) with the block relaxation matrix of
  * Eq. (99)), the equilibrium of Eq. (7), the source of Eq. (8), the correction G of
@@ -15,7 +15,8 @@
  * Discretisation choices where the paper leaves the detail open:
  *   - d_t B in G is the backward difference B(phi(t)) - B(phi(t-1)); at the first step
  *     phi(t-1) is phi0, so G starts at zero.
- *   - Sources are time independent, so the Scheme 2 derivative term (Remark III) is 0.
+ *   - A source that changes in time or with phi enters through Scheme 2 (Remark III):
+ *     S(t) + (S(t) - S(t-1))/2, with S(t-1) taken at phi(t-1) and S(-1) = S(0).
  *   - A diagonal link leaving through a corner point bounces back with the mean of the
  *     two walls' values.
  *   - Node x = (i, j) sits at the cell centre (i + 1/2, j + 1/2); walls lie at 0 and nx
@@ -81,11 +82,16 @@ typedef struct {
     size_t workspace_bytes; /* size of workspace in bytes (ignored when workspace is NULL) */
 } btrt_grid_t;
 
-/* B(phi) = a*phi + b*phi^2/2, per component (Eq. (1)). Linear convection with velocity u
- * is a = u, b = 0; the Burgers flux (phi^2/2)*c is a = 0, b = c. */
+/* B(phi) = a*phi + b*phi^2/2 + c*|phi|^q, per component (Eq. (1)). Linear convection with
+ * velocity u is a = u, b = 0; the Burgers flux (phi^2/2)*c is a = 0, b = c; the convection
+ * a phi^delta d_x phi of the Burgers-Fisher equation (Eq. (67)) is c = (a/(delta+1), 0),
+ * q = delta + 1. q is read only when c != 0 and must then be >= 1. A nonzero c selects the
+ * general node model (BTRT_F64 or BTRT_F32 storage, single handles only). */
 typedef struct {
     double a[2];
     double b[2];
+    double c[2];
+    double q;
 } btrt_flux_t;
 
 /* A(x, phi) = A0 * (1 + beta*phi^2) (Eq. (1)) with A0 = [[k11, k12], [k12, k22]], or, when
@@ -103,16 +109,22 @@ typedef struct {
     int32_t kind; /* BTRT_D_PHI_I */
 } btrt_dterm_t;
 
-/* Source S of Eq. (8): S(x, t) = exp(growth * t) * S0(x) at step t (t = 0, 1, ...), with
- * S0 = field[j*nx + i] (FIELD, copied at create) or amp*sin(kx pi (i+1/2)/nx)*sin(ky pi
- * (j+1/2)/ny) (SIN). A source that changes in time enters with the Scheme 2 correction of
- * Remark III, S(t) + (S(t) - S(t-1))/2, with S(-1) = S(0). growth = 0: time independent. */
+/* Source S of Eq. (8): S(x, phi, t) = exp(growth * t) * S0(x) + r*phi*(1 - |phi|^p) at step t
+ * (t = 0, 1, ...), with S0 = 0 (NONE), field[j*nx + i] (FIELD, copied at create) or
+ * amp*sin(kx pi (i+1/2)/nx)*sin(ky pi (j+1/2)/ny) (SIN). The phi-dependent part is the reaction
+ * of the Burgers-Fisher equation (Eq. (67), r = b dt, p = delta) and is evaluated at the node's
+ * phi(t). A source that changes in time or with phi enters with the Scheme 2 correction of
+ * Remark III, S(t) + (S(t) - S(t-1))/2, with S(t-1) at phi(t-1) and S(-1) = S(0).
+ * growth = 0: S0 time independent. p is read only when r != 0 and must then be > 0; a nonzero
+ * r selects the general node model (BTRT_F64 or BTRT_F32 storage, single handles only). */
 typedef struct {
     int32_t kind; /* BTRT_SRC_NONE, BTRT_SRC_FIELD or BTRT_SRC_SIN */
     double amp;
     int32_t kx, ky;
     const double* field;
     double growth;
+    double r;
+    double p;
 } btrt_source_t;
 
 /* Sides in the order x-, x+, y-, y+. A periodic side must be paired with its opposite. */
@@ -150,7 +162,9 @@ typedef struct {
 
 /* Checks a problem and fills *info (optional) without touching any device.
  * Errors: BTRT_E_INVAL for sizes out of range, unpaired periodic sides, A (or any node of an
- * A0 field) not SPD or beta < 0, rates outside (0, 2), BTRT_K2_HBB with a non-isotropic,
+ * A0 field) not SPD or beta < 0, rates outside (0, 2), a power-law exponent q < 1 or a
+ * reaction exponent p <= 0 where used, the general node model with BTRT_F16DEV or
+ * BTRT_BF16DEV, BTRT_K2_HBB with a non-isotropic,
  * phi-dependent or space-dependent A, an unsupported D or source kind, or non-finite values. */
 int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
                   const btrt_dterm_t* D, const btrt_source_t* R, const btrt_bc_t* bc,
@@ -169,8 +183,26 @@ int btrt_create(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t
                 const btrt_relax_t* relax, const double* phi0, btrt_t** out);
 
 /* Enqueues n >= 0 time steps (collide, stream, bounce back) on the handle's stream and
- * returns without waiting. */
+ * returns without waiting. With a wall schedule (btrt_set_walls) the steps must lie inside it:
+ * BTRT_E_INVAL, with nothing enqueued, otherwise. */
 int btrt_step(btrt_t* h, int64_t n);
+
+/* Dirichlet values that change along the walls and in time (Eqs. (54)-(56) with phi_w(x, t),
+ * as the Burgers-Fisher problem of Eqs. (67)-(69) needs) for the next `steps` >= 1 steps.
+ * values[k*P + q], P = 2*(nx + ny): for the k-th step from now (k = 0 .. steps-1), the values
+ * phi_w of the populations that the bounce-back returns into the grid at the end of that step
+ * (time t + k + 1), along side x- at rows j (q = j), x+ at rows j (q = ny + j), y- at columns i
+ * (q = 2 ny + i) and y+ at columns i (q = 2 ny + nx + i); entries of periodic sides are
+ * ignored. A link of node (i, j) leaving through an x side takes that side's value at row j,
+ * through a y side the value at column i, and a diagonal link through a corner point the mean
+ * of the two. The values are copied (host memory, read during the call); the handle allocates
+ * device memory for them (P * (steps + 1) values, freed by the next call or btrt_destroy).
+ * Once set, btrt_step, btrt_solve and btrt_tune may advance at most `steps` steps past the
+ * step count of this call; a new call continues from the current step. Selects the general
+ * node model from the next step on. Errors: BTRT_E_INVAL for NULL values, steps < 1,
+ * non-finite values, or a BTRT_F16DEV / BTRT_BF16DEV handle; BTRT_E_NOMEM; BTRT_E_DEVICE.
+ * Synchronises. */
+int btrt_set_walls(btrt_t* h, const double* values, int64_t steps);
 
 /* Shape of the sweep launches btrt_step makes. Every shape gives bitwise identical results;
  * only the speed differs. Zero fields are chosen by the library for the grid.
@@ -285,7 +317,8 @@ typedef struct {
  * library creates one). Device memory is allocated by the library (the sum of the instances'
  * btrt_workspace_size plus small tables). Errors: any instance failing btrt_validate or
  * holding a non-finite phi0 -> BTRT_E_INVAL (btrt_last_error names the instance); mixed
- * precisions, an A0 field or a growing source -> BTRT_E_INVAL; BTRT_E_DEVICE; BTRT_E_NOMEM.
+ * precisions, an A0 field, a growing source or the general node model (a power-law flux or a
+ * phi-dependent source) -> BTRT_E_INVAL; BTRT_E_DEVICE; BTRT_E_NOMEM.
  * Synchronises. */
 int btrt_batch_create(int32_t n, const btrt_problem_t* problems, int32_t device, void* stream,
                       btrt_batch_t** out);
@@ -374,8 +407,8 @@ int btrt_server_create(const btrt_server_opts_t* opts, btrt_server_t** out);
 
 /* Queues one request: solve p until the residual is <= tol or max_steps steps (rounded up to
  * whole rounds). p's host arrays are copied. *id receives the request id. Errors: those of
- * btrt_validate, non-finite phi0, a precision other than the server's, an A0 field or a
- * growing source -> BTRT_E_INVAL; a footprint larger than the server's memory -> BTRT_E_NOMEM. */
+ * btrt_validate, non-finite phi0, a precision other than the server's, an A0 field, a
+ * growing source or the general node model -> BTRT_E_INVAL; a footprint larger than the server's memory -> BTRT_E_NOMEM. */
 int btrt_server_submit(btrt_server_t* s, const btrt_problem_t* p, double tol, int64_t max_steps, int64_t* id);
 
 /* One scheduling round (see above). Reports resident and queued counts. Synchronises. */

@@ -24,7 +24,8 @@ D_PHI_I = 0
 K2_VALUE, K2_HBB = 0, 1
 
 # Every function include/btrt.h declares.
-EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_launch", "btrt_get_launch",
+EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "btrt_set_walls", "btrt_set_launch",
+           "btrt_get_launch",
            "btrt_set_fusion", "btrt_tune", "btrt_field",
            "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
            "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error",
@@ -42,7 +43,8 @@ class Grid(ctypes.Structure):
 
 
 class Flux(ctypes.Structure):
-    _fields_ = [("a", ctypes.c_double * 2), ("b", ctypes.c_double * 2)]
+    _fields_ = [("a", ctypes.c_double * 2), ("b", ctypes.c_double * 2), ("c", ctypes.c_double * 2),
+                ("q", ctypes.c_double)]
 
 
 class Diff(ctypes.Structure):
@@ -56,7 +58,8 @@ class DTerm(ctypes.Structure):
 
 class Source(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("amp", ctypes.c_double), ("kx", ctypes.c_int32),
-                ("ky", ctypes.c_int32), ("field", ctypes.POINTER(ctypes.c_double)), ("growth", ctypes.c_double)]
+                ("ky", ctypes.c_int32), ("field", ctypes.POINTER(ctypes.c_double)), ("growth", ctypes.c_double),
+                ("r", ctypes.c_double), ("p", ctypes.c_double)]
 
 
 class BC(ctypes.Structure):
@@ -155,6 +158,7 @@ def lib() -> ctypes.CDLL:
             "btrt_workspace_size": ([P(Grid), P(Diff), P(Source)], ctypes.c_size_t),
             "btrt_create": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, P(hp)], ctypes.c_int),
             "btrt_step": ([hp, ctypes.c_int64], ctypes.c_int),
+            "btrt_set_walls": ([hp, dp, ctypes.c_int64], ctypes.c_int),
             "btrt_set_fusion": ([hp, ctypes.c_int32], ctypes.c_int),
             "btrt_set_launch": ([hp, P(Launch)], ctypes.c_int),
             "btrt_get_launch": ([hp, P(Launch)], ctypes.c_int),
@@ -209,18 +213,21 @@ def _dptr(a: np.ndarray):
 class Problem:
     """The arguments of btrt_create (Eq. (1) with D = phi I), as ctypes structures.
 
-    flux_a, flux_b: B(phi) = a phi + b phi^2/2; A0 = (k11, k12, k22), beta: A = A0 (1 + beta phi^2);
-    A0_field: None or an (ny, nx, 3) array of per-node (a11, a12, a22) replacing A0;
-    source: None, an (ny, nx) array, ("sin", amp, kx, ky) or ("field", array, growth) for
-    S(x, t) = exp(growth t) array(x); bc_type/bc_value for sides x-, x+, y-, y+; k0;
-    k2: "hbb" (Eq. (62)), a scalar (K2 = k2 Ihat) or four entries.
+    flux_a, flux_b, flux_c, flux_q: B(phi) = a phi + b phi^2/2 + c |phi|^q; A0 = (k11, k12, k22),
+    beta: A = A0 (1 + beta phi^2); A0_field: None or an (ny, nx, 3) array of per-node
+    (a11, a12, a22) replacing A0; source: None, an (ny, nx) array, ("sin", amp, kx, ky) or
+    ("field", array, growth) for S(x, t) = exp(growth t) array(x); src_r, src_p: the source gains
+    r phi (1 - |phi|^p); bc_type/bc_value for sides x-, x+, y-, y+; k0; k2: "hbb" (Eq. (62)), a
+    scalar (K2 = k2 Ihat) or four entries.
     """
 
     def __init__(self, nx: int, ny: int, *, precision: int = F64, flux_a=(0.0, 0.0), flux_b=(0.0, 0.0),
                  A0=(0.0, 0.0, 0.0), beta: float = 0.0, A0_field=None, source=None, bc_type=(PERIODIC,) * 4,
-                 bc_value=(0.0,) * 4, k0: float = 1.0, k2=1.0, check_interval: int = 1000, device: int = 0):
+                 bc_value=(0.0,) * 4, k0: float = 1.0, k2=1.0, check_interval: int = 1000, device: int = 0,
+                 flux_c=(0.0, 0.0), flux_q: float = 1.0, src_r: float = 0.0, src_p: float = 1.0):
         self.grid = Grid(int(nx), int(ny), int(precision), int(device), None, None, 0)
-        self.flux = Flux((ctypes.c_double * 2)(*flux_a), (ctypes.c_double * 2)(*flux_b))
+        self.flux = Flux((ctypes.c_double * 2)(*flux_a), (ctypes.c_double * 2)(*flux_b),
+                         (ctypes.c_double * 2)(*flux_c), float(flux_q))
         self._afield = None
         if A0_field is not None:
             self._afield = np.ascontiguousarray(A0_field, dtype=np.float64).reshape(ny, nx, 3)
@@ -229,16 +236,18 @@ class Problem:
         self.dterm = DTerm(D_PHI_I)
         self._field = None
         if source is None:
-            self.source = Source(SRC_NONE, 0.0, 0, 0, None, 0.0)
+            self.source = Source(SRC_NONE, 0.0, 0, 0, None, 0.0, 0.0, 1.0)
         elif isinstance(source, tuple) and source and source[0] == "sin":
             _, amp, kx, ky = source
-            self.source = Source(SRC_SIN, float(amp), int(kx), int(ky), None, 0.0)
+            self.source = Source(SRC_SIN, float(amp), int(kx), int(ky), None, 0.0, 0.0, 1.0)
         else:
             growth = 0.0
             if isinstance(source, tuple) and source and source[0] == "field":
                 _, source, growth = source
             self._field = np.ascontiguousarray(source, dtype=np.float64).reshape(ny, nx)
-            self.source = Source(SRC_FIELD, 0.0, 0, 0, _dptr(self._field), float(growth))
+            self.source = Source(SRC_FIELD, 0.0, 0, 0, _dptr(self._field), float(growth), 0.0, 1.0)
+        self.source.r = float(src_r)
+        self.source.p = float(src_p)
         self.bc = BC((ctypes.c_int32 * 4)(*bc_type), (ctypes.c_double * 4)(*bc_value))
         if isinstance(k2, str):
             assert k2 == "hbb"
@@ -301,6 +310,15 @@ class Solver:
     # -- calls of include/btrt.h -----------------------------------------------------------
     def step(self, n: int) -> "Solver":
         _check(lib().btrt_step(self.h, int(n)), "btrt_step")
+        return self
+
+    def set_walls(self, values: np.ndarray) -> "Solver":
+        """btrt_set_walls: Dirichlet values for the next len(values) steps, each row x- (ny),
+        x+ (ny), y- (nx), y+ (nx)."""
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        P = 2 * (self.problem.nx + self.problem.ny)
+        v = v.reshape(-1, P)
+        _check(lib().btrt_set_walls(self.h, _dptr(v), int(v.shape[0])), "btrt_set_walls")
         return self
 
     def set_fusion(self, steps_per_launch: int) -> "Solver":
@@ -386,7 +404,13 @@ def problem_from_workload(w, precision: int = F64, device: int = 0, check_interv
     """btrt_create arguments for a workloads.Workload."""
     return Problem(w.nx, w.ny, precision=precision, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta,
                    A0_field=getattr(w, "A0_field", None), source=w.source, bc_type=w.bc_type,
-                   bc_value=w.bc_value, k0=w.k0, k2=w.k2, check_interval=check_interval, device=device)
+                   bc_value=w.bc_value, k0=w.k0, k2=w.k2, check_interval=check_interval, device=device,
+                   flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p)
+
+
+def wall_schedule(w, start: int, steps: int) -> np.ndarray:
+    """Rows start .. start+steps-1 of a workload's Dirichlet schedule, for Solver.set_walls."""
+    return np.stack([np.asarray(w.walls(k), dtype=np.float64) for k in range(start, start + steps)])
 
 
 class Batch:

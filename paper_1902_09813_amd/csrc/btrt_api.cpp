@@ -24,6 +24,7 @@ struct btrt {
     bool own_mem = false;
     int check_interval = 1000;
     btrtk::LaunchCfg launch{};  // requested launch shape (zero fields: automatic)
+    void* wsched = nullptr;     // device wall schedule of btrt_set_walls (owned)
     Instance inst;
 };
 
@@ -36,6 +37,10 @@ using btrtk::LaunchCfg;
 int enqueue_steps(btrt* h, const LaunchCfg& want, int64_t n)
 {
     if (n <= 0) return BTRT_OK;
+    if (n > h->inst.wall_limit - h->inst.step)
+        return fail(BTRT_E_INVAL, "%lld steps from step %lld go past the wall schedule (it ends at step %lld)",
+                    static_cast<long long>(n), static_cast<long long>(h->inst.step),
+                    static_cast<long long>(h->inst.wall_limit));
     const LaunchCfg c = instance_resolve(h->inst, want);
     for (int64_t i = 0; i < n;) {
         LaunchCfg k = c;
@@ -82,6 +87,7 @@ void release(btrt* h)
     DeviceGuard g(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->own_mem && h->mem) (void)hipFree(h->mem);
+    if (h->wsched) (void)hipFree(h->wsched);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -178,6 +184,60 @@ int btrt_step(btrt_t* h, int64_t n)
     return rc == BTRT_OK ? ok() : rc;
 }
 
+int btrt_set_walls(btrt_t* h, const double* values, int64_t steps)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    Instance& I = h->inst;
+    if (!values) return fail(BTRT_E_INVAL, "values is NULL");
+    if (steps < 1) return fail(BTRT_E_INVAL, "steps = %lld < 1", static_cast<long long>(steps));
+    if (I.precision != BTRT_F64 && I.precision != BTRT_F32)
+        return fail(BTRT_E_INVAL, "wall schedules need BTRT_F64 or BTRT_F32 storage");
+    const int64_t P = I.wall_entry_values();
+    const bool wall_side[4] = {!I.perx, !I.perx, !I.pery, !I.pery};
+    const int64_t side_begin[5] = {0, I.ny, 2LL * I.ny, 2LL * I.ny + I.nx, P};
+    for (int64_t k = 0; k < steps; ++k)
+        for (int q = 0; q < 4; ++q) {
+            if (!wall_side[q]) continue;
+            for (int64_t e = side_begin[q]; e < side_begin[q + 1]; ++e)
+                if (!std::isfinite(values[k * P + e]))
+                    return fail(BTRT_E_INVAL, "non-finite wall value at step %lld, entry %lld",
+                                static_cast<long long>(k), static_cast<long long>(e));
+        }
+    const size_t es = I.precision == BTRT_F64 ? 8 : 4;
+    const size_t bytes = static_cast<size_t>(P) * static_cast<size_t>(steps + 1) * es;
+    DeviceGuard g(h->device);
+    if (g.status() != hipSuccess) return hip_fail(g.status(), "hipSetDevice");
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BTRT_E_NOMEM, "hipMalloc of %zu bytes for the wall schedule failed", bytes);
+    }
+    char* dst = static_cast<char*>(mem);
+    // Entry 0: the values the next pull reads (the step that ends at the current count), from
+    // the current table, or the per-side constants the populations were initialised with.
+    hipError_t e;
+    if (I.gen && I.wtab) {
+        const char* cur = I.wtab + static_cast<size_t>(I.step - I.wall_t0) * I.wall_stride * es;
+        e = hipMemcpyAsync(dst, cur, static_cast<size_t>(P) * es, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    } else {
+        e = upload_wall_entry(I, dst, h->stream);
+    }
+    if (e == hipSuccess) e = upload_wall_values(I, values, static_cast<size_t>(P * steps), dst + P * es, h->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "wall schedule upload");
+    }
+    if (h->wsched) (void)hipFree(h->wsched);  // the stream is idle: nothing reads it any more
+    h->wsched = mem;
+    I.gen = true;
+    I.wtab = dst;
+    I.wall_t0 = I.step;
+    I.wall_limit = I.step + steps;
+    I.wall_stride = static_cast<int>(P);
+    return ok();
+}
+
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch)
 {
     if (!h) return fail(BTRT_E_STATE, "NULL handle");
@@ -208,6 +268,7 @@ int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_
 {
     if (!h) return fail(BTRT_E_STATE, "NULL handle");
     if (max_steps < 0) return fail(BTRT_E_INVAL, "max_steps < 0");
+    max_steps = std::min<int64_t>(max_steps, h->inst.wall_limit - h->inst.step);  // stay inside a wall schedule
     DeviceGuard g(h->device);
     // Candidates: one step per launch, the two-step LDS tile, and strip walkers over steps per
     // launch x strip rows x strips per group. Each runs one untimed launch and kReps timed ones.

@@ -58,8 +58,10 @@ int btrt_batch_create(int32_t n, const btrt_problem_t* problems, int32_t device,
         if (p.grid.precision != precision) return fail(BTRT_E_INVAL, "instance %d: precision differs from instance 0", i);
         if (precision != BTRT_F64 && precision != BTRT_F32)
             return fail(BTRT_E_INVAL, "batches take BTRT_F64 or BTRT_F32 storage");
-        if (res[i].afield || res[i].growth != 0.0)
-            return fail(BTRT_E_INVAL, "instance %d: batches take no A0 field and no growing source", i);
+        if (res[i].afield || res[i].growth != 0.0 || res[i].gen)
+            return fail(BTRT_E_INVAL,
+                        "instance %d: batches take no A0 field, growing source, power-law flux or phi-dependent source",
+                        i);
         offs[i] = total;
         total += align_up(layout_for(p.grid.nx, p.grid.ny, precision, p.R.kind).total);
     }

@@ -78,9 +78,13 @@ __device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int 
 template <typename T_>
 struct Plain {
     using T = T_;
+    // With a wall table (general model) an edge node takes its Dirichlet values from the table
+    // entry of the launch's first step.
     __device__ __forceinline__ static void pull(const SweepArgs<T>& a, int x, int y, T f[9])
     {
-        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, a.wall, f);
+        T w[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
+        if (a.wtab != nullptr && (x == 0 || y == 0 || x == a.nx - 1 || y == a.ny - 1)) table_walls(a, x, y, 0, w);
+        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, w, f);
     }
     __device__ __forceinline__ static void settle(const SweepArgs<T>&, T*, T) {}
     // Raw loads of one node's pull (see walk_load): value read for each direction.
@@ -290,16 +294,20 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         const int l = (iy + 1) * EX + ix + 1;
         const bool okxm = a.perx || gx > 0, okxp = a.perx || gx < nx - 1;
         const bool okym = a.pery || gy > 0, okyp = a.pery || gy < ny - 1;
+        T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
+        if constexpr ((KM & kGen) != 0) {
+            if (!(okxm && okxp && okym && okyp)) table_walls(a, gx, gy, 1, wv);
+        }
         T g[9];
         g[0] = lf[0][l];
-        g[1] = okxm ? lf[1][l - 1] : bounce(lf[3][l], tw1, a.wall[0]);
-        g[2] = okym ? lf[2][l - EX] : bounce(lf[4][l], tw1, a.wall[2]);
-        g[3] = okxp ? lf[3][l + 1] : bounce(lf[1][l], tw1, a.wall[1]);
-        g[4] = okyp ? lf[4][l + EX] : bounce(lf[2][l], tw1, a.wall[3]);
-        g[5] = (okxm && okym) ? lf[5][l - EX - 1] : bounce(lf[7][l], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
-        g[6] = (okxp && okym) ? lf[6][l - EX + 1] : bounce(lf[8][l], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
-        g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
-        g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+        g[1] = okxm ? lf[1][l - 1] : bounce(lf[3][l], tw1, wv[0]);
+        g[2] = okym ? lf[2][l - EX] : bounce(lf[4][l], tw1, wv[2]);
+        g[3] = okxp ? lf[3][l + 1] : bounce(lf[1][l], tw1, wv[1]);
+        g[4] = okyp ? lf[4][l + EX] : bounce(lf[2][l], tw1, wv[3]);
+        g[5] = (okxm && okym) ? lf[5][l - EX - 1] : bounce(lf[7][l], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
+        g[6] = (okxp && okym) ? lf[6][l - EX + 1] : bounce(lf[8][l], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
+        g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
+        g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
         const int n = gy * a.pitch + gx;
         const T phi = collide<T, SRC, KM>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy, 1), n);
         F::put(a, n, g, phi);
@@ -424,15 +432,19 @@ __device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], 
     }
     const bool okym = WALLS ? row.okm : true, okyp = WALLS ? row.okp : true;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
+    T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
+    if constexpr (WALLS && (KM & kGen) != 0) {
+        if (!(okxm && okxp && okym && okyp)) table_walls(a, x, row.y, lvl, wv);
+    }
     g[0] = m[0];
-    g[1] = okxm ? s1 : bounce(m[3], tw1, a.wall[0]);
-    g[2] = okym ? up[0] : bounce(m[4], tw1, a.wall[2]);
-    g[3] = okxp ? s3 : bounce(m[1], tw1, a.wall[1]);
-    g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, a.wall[3]);
-    g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
-    g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
-    g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
-    g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+    g[1] = okxm ? s1 : bounce(m[3], tw1, wv[0]);
+    g[2] = okym ? up[0] : bounce(m[4], tw1, wv[2]);
+    g[3] = okxp ? s3 : bounce(m[1], tw1, wv[1]);
+    g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, wv[3]);
+    g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
+    g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
+    g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
+    g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
     const int n = row.y * a.pitch + x;
     return collide<T, SRC, KM>(a, g, mid.phi, source_at<T, SRC>(a, n, x, row.y, lvl), n);
 }
@@ -444,11 +456,12 @@ __device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], 
 template <typename F>
 struct WalkIn {
     typename F::Raw raw;
-    typename F::T phi;  // phi(t-1) of the node
-    int ok;             // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
+    typename F::T phi;   // phi(t-1) of the node
+    typename F::T w[4];  // general model: the node's Dirichlet values from the wall table
+    int ok;              // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
 };
 
-template <typename F, bool WALLS>
+template <typename F, bool WALLS, bool GEN>
 __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int x, bool colok, int r, WalkIn<F>& in)
 {
     const WalkRow w = walk_row(r, a.ny, WALLS ? a.pery : 1);
@@ -474,12 +487,13 @@ __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int
                         ok5 ? rm + xm : n, ok6 ? rm + xp : n, ok7 ? rp + xp : n, ok8 ? rp + xm : n};
     F::fetch(a, plane, idx, in.raw);
     in.phi = a.phi_prev[n];
+    if constexpr (WALLS && GEN) table_walls(a, x, y, 0, in.w);  // x, y are in the grid
     in.ok = (okxm ? 1 : 0) | (okxp ? 2 : 0) | (okym ? 4 : 0) | (okyp ? 8 : 0) | ((colok && w.ok) ? 16 : 0);
 }
 
 // f(x, t) from the raw loads (bounce-back at Dirichlet walls, Eqs. (54)-(56)); zeros where the
 // lane is not a node.
-template <typename F, bool WALLS>
+template <typename F, bool WALLS, bool GEN>
 __device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, const WalkIn<F>& in,
                                             typename F::T f[9], typename F::T& phi_prev)
 {
@@ -497,15 +511,20 @@ __device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, c
     T v[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) v[i] = F::value(a, in.raw, i, opp[i], !ok[i]);
+    T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
+    if constexpr (GEN) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wv[q] = in.w[q];
+    }
     f[0] = v[0];
-    f[1] = ok[1] ? v[1] : bounce(v[1], tw1, a.wall[0]);
-    f[2] = ok[2] ? v[2] : bounce(v[2], tw1, a.wall[2]);
-    f[3] = ok[3] ? v[3] : bounce(v[3], tw1, a.wall[1]);
-    f[4] = ok[4] ? v[4] : bounce(v[4], tw1, a.wall[3]);
-    f[5] = ok[5] ? v[5] : bounce(v[5], tw5, wall_value(!okxm, !okym, a.wall[0], a.wall[2]));
-    f[6] = ok[6] ? v[6] : bounce(v[6], tw5, wall_value(!okxp, !okym, a.wall[1], a.wall[2]));
-    f[7] = ok[7] ? v[7] : bounce(v[7], tw5, wall_value(!okxp, !okyp, a.wall[1], a.wall[3]));
-    f[8] = ok[8] ? v[8] : bounce(v[8], tw5, wall_value(!okxm, !okyp, a.wall[0], a.wall[3]));
+    f[1] = ok[1] ? v[1] : bounce(v[1], tw1, wv[0]);
+    f[2] = ok[2] ? v[2] : bounce(v[2], tw1, wv[2]);
+    f[3] = ok[3] ? v[3] : bounce(v[3], tw1, wv[1]);
+    f[4] = ok[4] ? v[4] : bounce(v[4], tw1, wv[3]);
+    f[5] = ok[5] ? v[5] : bounce(v[5], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
+    f[6] = ok[6] ? v[6] : bounce(v[6], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
+    f[7] = ok[7] ? v[7] : bounce(v[7], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
+    f[8] = ok[8] ? v[8] : bounce(v[8], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
     phi_prev = in.phi;
     if (!node) {
 #pragma unroll
@@ -537,9 +556,10 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
                                           WalkIn<F>& in, WalkState<typename F::T, K>& st)
 {
     using T = typename F::T;
+    constexpr bool GEN = (KM & kGen) != 0;
     __builtin_amdgcn_s_barrier();
     Level<T> lev;
-    walk_finish<F, WALLS>(a, in, lev.f, lev.phi);
+    walk_finish<F, WALLS, GEN>(a, in, lev.f, lev.phi);
 
     // Level 1: row r from global memory.
     {
@@ -557,7 +577,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
     // covers memory operations issued at least one row earlier.
     if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
     st.out_n = -1;
-    if (r + kAhead<T> < r1) walk_load<F, WALLS>(a, L.x, L.colok, r + kAhead<T>, in);
+    if (r + kAhead<T> < r1) walk_load<F, WALLS, GEN>(a, L.x, L.colok, r + kAhead<T>, in);
 
     // Levels 2..K: row r-(l-1) from the rows of level l-1. Level l is valid from row
     // ys-(K-l) on; the first rows of the walk (while the levels fill) are skipped, which leaves
@@ -638,9 +658,10 @@ __device__ __forceinline__ void walk_strip(const SweepArgs<typename F::T>& a, in
 
     // Loads of rows r0, r0+2, ... go to in[0] and of rows r0+1, r0+3, ... to in[1] with two
     // rows in flight; with one row in flight in[0] serves every row.
+    constexpr bool GEN = (KM & kGen) != 0;
     WalkIn<F> in[kAhead<T>];
-    walk_load<F, WALLS>(a, L.x, L.colok, r0, in[0]);
-    if (kAhead<T> == 2 && r0 + 1 < r1) walk_load<F, WALLS>(a, L.x, L.colok, r0 + 1, in[kAhead<T> - 1]);
+    walk_load<F, WALLS, GEN>(a, L.x, L.colok, r0, in[0]);
+    if (kAhead<T> == 2 && r0 + 1 < r1) walk_load<F, WALLS, GEN>(a, L.x, L.colok, r0 + 1, in[kAhead<T> - 1]);
     for (int r = r0; r < r1; r += 2) {
         walk_step<F, SRC, KM, K, WALLS, 0>(a, L, r, r1, in[0], st);
         if (r + 1 < r1) walk_step<F, SRC, KM, K, WALLS, 1>(a, L, r + 1, r1, in[kAhead<T> - 1], st);
@@ -902,6 +923,14 @@ hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t 
         BTRT_BY_SRC(kK1Const, FN, __VA_ARGS__);                                  \
     } while (0)
 
+// The same over the general node model (K1 mode | kGen).
+#define BTRT_BY_VARIANT_GEN(FN, ...)                                             \
+    do {                                                                         \
+        if (kmode == (kK1Field | kGen)) BTRT_BY_SRC(kK1Field | kGen, FN, __VA_ARGS__); \
+        if (kmode == (kK1Phi | kGen)) BTRT_BY_SRC(kK1Phi | kGen, FN, __VA_ARGS__);     \
+        BTRT_BY_SRC(kK1Const | kGen, FN, __VA_ARGS__);                           \
+    } while (0)
+
 template <typename F>
 hipError_t sweep_with(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg,
                       hipStream_t s)
@@ -915,6 +944,20 @@ LaunchCfg resolve_with(const SweepArgs<typename F::T>& a, int src_kind, int kmod
     BTRT_BY_VARIANT(resolve_variant, a, cfg);
 }
 
+template <typename F>
+hipError_t sweep_with_gen(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg,
+                          hipStream_t s)
+{
+    BTRT_BY_VARIANT_GEN(sweep_variant, a, cfg, s);
+}
+
+template <typename F>
+LaunchCfg resolve_with_gen(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg)
+{
+    BTRT_BY_VARIANT_GEN(resolve_variant, a, cfg);
+}
+
+#undef BTRT_BY_VARIANT_GEN
 #undef BTRT_BY_VARIANT
 #undef BTRT_BY_SRC
 
@@ -930,5 +973,10 @@ LaunchCfg resolve_f64(const SweepArgs<double>& a, int src_kind, int kmode, const
 LaunchCfg resolve_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 LaunchCfg resolve_f16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 LaunchCfg resolve_bf16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
+// The general node model (kmode carries kGen), plain storage only (btrt_sweep_gen_<format>.hip).
+hipError_t sweep_gen_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+hipError_t sweep_gen_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+LaunchCfg resolve_gen_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg);
+LaunchCfg resolve_gen_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 
 }  // namespace btrtk

@@ -90,6 +90,7 @@ Layout layout_for(int nx, int ny, int precision, int src_kind, bool afield)
         L.src_y = take(static_cast<size_t>(ny) * ps);
     }
     L.afield = afield ? take(3 * plane * ps) : 0;
+    L.wall0 = take(2 * (static_cast<size_t>(nx) + static_cast<size_t>(ny)) * ps);
     L.total = off;
     return L;
 }
@@ -116,7 +117,20 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
                     grid->precision);
     if (!grid_ok(grid)) return fail(BTRT_E_INVAL, "grid %d x %d exceeds 2^31 - 1 nodes", grid->nx, grid->ny);
     for (int a = 0; a < 2; ++a)
-        if (!is_finite(B->a[a]) || !is_finite(B->b[a])) return fail(BTRT_E_INVAL, "non-finite flux coefficient");
+        if (!is_finite(B->a[a]) || !is_finite(B->b[a]) || !is_finite(B->c[a]))
+            return fail(BTRT_E_INVAL, "non-finite flux coefficient");
+    const bool power = B->c[0] != 0.0 || B->c[1] != 0.0;
+    if (power && !(is_finite(B->q) && B->q >= 1.0))
+        return fail(BTRT_E_INVAL, "power-law flux exponent q = %g: must be finite and >= 1", B->q);
+    bool reaction = false;
+    if (R) {
+        if (!is_finite(R->r)) return fail(BTRT_E_INVAL, "non-finite reaction rate r");
+        reaction = R->r != 0.0;
+        if (reaction && !(is_finite(R->p) && R->p > 0.0))
+            return fail(BTRT_E_INVAL, "reaction exponent p = %g: must be finite and > 0", R->p);
+    }
+    if ((power || reaction) && grid->precision != BTRT_F64 && grid->precision != BTRT_F32)
+        return fail(BTRT_E_INVAL, "a power-law flux or a phi-dependent source needs BTRT_F64 or BTRT_F32 storage");
     if (!is_finite(K->beta)) return fail(BTRT_E_INVAL, "non-finite beta");
     if (K->field) {
         // Eq. (73)/(74): every node's A0 must be a finite symmetric positive definite tensor.
@@ -174,6 +188,7 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
     res->afield = K->field != nullptr;
     res->k1_per_node = K->beta != 0.0 || res->afield;
     res->growth = R && R->kind != BTRT_SRC_NONE ? R->growth : 0.0;
+    res->gen = power || reaction;
 
     if (relax->k2_rule == BTRT_K2_HBB) {
         // Eq. (62) removes the bounce-back slip for K1 = k1 I (Section 3).
@@ -273,6 +288,13 @@ void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const bt
     a.src_y = I.kind == kSrcSep ? reinterpret_cast<const T*>(I.mem + I.L.src_y) : nullptr;
     a.afield = I.afield ? reinterpret_cast<const T*>(I.mem + I.L.afield) : nullptr;
     for (int l = 0; l < btrtk::kMaxFuse; ++l) a.sfac[l] = T(1);
+    a.fcx = static_cast<T>(B->c[0]);
+    a.fcy = static_cast<T>(B->c[1]);
+    a.fq = static_cast<T>(B->c[0] != 0.0 || B->c[1] != 0.0 ? B->q : 1.0);
+    a.rr = static_cast<T>(R ? R->r : 0.0);
+    a.rp = static_cast<T>(R && R->r != 0.0 ? R->p : 1.0);
+    a.wtab = nullptr;  // set per launch (sweep_args) for the general node model
+    a.wstride = 0;
     // Non-temporal stores once the two buffers of populations and phi exceed the 256 MB
     // Infinity Cache.
     const double state_bytes = 2.0 * static_cast<double>(I.plane) * (9.0 * pop_bytes(I.precision) + sizeof(T));
@@ -297,6 +319,11 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
     I.k1_per_node = r.k1_per_node;
     I.afield = r.afield;
     I.growth = r.growth;
+    I.gen = r.gen;
+    I.wtab = nullptr;
+    I.wall_t0 = 0;
+    I.wall_limit = INT64_MAX;
+    I.wall_stride = 0;
     I.perx = bc->type[0] == BTRT_PERIODIC;
     I.pery = bc->type[2] == BTRT_PERIODIC;
     for (int q = 0; q < 4; ++q) I.wall[q] = bc->type[q] == BTRT_DIRICHLET ? bc->value[q] : 0.0;
@@ -372,16 +399,24 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         fill_constants<double>(I, I.a64, B, K, R, r);
     else
         fill_constants<float>(I, I.a32, B, K, R, r);
+    // The general node model reads its Dirichlet values from a wall table: one entry holding
+    // the per-side constants, used by every step until a schedule replaces it.
+    if (I.gen) {
+        err = upload_wall_entry(I, I.mem + I.L.wall0, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return hip_fail(err, "wall table upload");
+        I.wtab = I.mem + I.L.wall0;
+    }
 
     err = hipMemcpyAsync(tmp, phi0, nn * sizeof(double), hipMemcpyHostToDevice, s);
     if (err != hipSuccess) return hip_fail(err, "phi0 upload");
     // The init kernel writes through a sweep's outputs: parity 1 outputs are f[0] and phi[0].
+    const double ab[4] = {B->a[0], B->a[1], B->b[0], B->b[1]};
+    const double cq[3] = {B->c[0], B->c[1], B->c[0] != 0.0 || B->c[1] != 0.0 ? B->q : 1.0};
     if (I.precision == BTRT_F64)
-        err = launch_init<double>(sweep_args<double>(I, 1), kFmtPlain, tmp, I.wall, B->a[0], B->a[1], B->b[0],
-                                  B->b[1], s);
+        err = launch_init<double>(sweep_args<double>(I, 1), kFmtPlain, tmp, I.wall, ab, cq, s);
     else
-        err = launch_init<float>(sweep_args<float>(I, 1), format_of(I.precision), tmp, I.wall, B->a[0], B->a[1],
-                                 B->b[0], B->b[1], s);
+        err = launch_init<float>(sweep_args<float>(I, 1), format_of(I.precision), tmp, I.wall, ab, cq, s);
     if (err != hipSuccess) return hip_fail(err, "init launch");
     err = hipMemcpyAsync(mem + I.L.snap, tmp, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (err != hipSuccess) return hip_fail(err, "snapshot copy");
@@ -403,7 +438,44 @@ SweepArgs<T> sweep_args(const Instance& I, int parity)
     a.fout = reinterpret_cast<T*>(I.mem + I.L.f[nxt]);
     a.phi_prev = reinterpret_cast<const T*>(I.mem + I.L.phi[parity]);
     a.phi_out = reinterpret_cast<T*>(I.mem + I.L.phi[nxt]);
+    if (I.gen && I.wtab) {
+        a.wtab = reinterpret_cast<const T*>(I.wtab) + (I.step - I.wall_t0) * I.wall_stride;
+        a.wstride = I.wall_stride;
+    }
     return a;
+}
+
+std::vector<double> wall_entry_constants(const Instance& I)
+{
+    std::vector<double> v(static_cast<size_t>(I.wall_entry_values()));
+    for (int j = 0; j < I.ny; ++j) {
+        v[j] = I.wall[0];
+        v[I.ny + j] = I.wall[1];
+    }
+    for (int i = 0; i < I.nx; ++i) {
+        v[2 * I.ny + i] = I.wall[2];
+        v[2 * I.ny + I.nx + i] = I.wall[3];
+    }
+    return v;
+}
+
+hipError_t upload_wall_values(const Instance& I, const double* v, size_t count, char* dst, hipStream_t s)
+{
+    hipError_t e;
+    std::vector<float> f;
+    if (I.precision == BTRT_F64) {
+        e = hipMemcpyAsync(dst, v, count * sizeof(double), hipMemcpyHostToDevice, s);
+    } else {
+        f.assign(v, v + count);
+        e = hipMemcpyAsync(dst, f.data(), count * sizeof(float), hipMemcpyHostToDevice, s);
+    }
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;  // the host buffers are locals
+}
+
+hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s)
+{
+    const std::vector<double> v = wall_entry_constants(I);
+    return upload_wall_values(I, v.data(), v.size(), dst, s);
 }
 
 template <typename T>

@@ -37,9 +37,10 @@ int format_of(int precision);
 
 // Byte offsets of every buffer of one instance inside its memory region.
 struct Layout {
-    size_t f[2], phi[2], snap, tmp, partial, result, src, src_y, afield, total;
+    size_t f[2], phi[2], snap, tmp, partial, result, src, src_y, afield, wall0, total;
 };
-// afield: three planes (a11, a12, a22) of a space-dependent A0(x).
+// afield: three planes (a11, a12, a22) of a space-dependent A0(x). wall0: one wall-table entry
+// (2 (nx + ny) values), the per-side constants of the general node model.
 Layout layout_for(int nx, int ny, int precision, int src_kind, bool afield = false);
 bool grid_ok(const btrt_grid_t* g);
 
@@ -51,6 +52,7 @@ struct Resolved {
     bool k1_per_node;  // beta > 0 or a per-node A0(x)
     bool afield;       // A0(x) given per node
     double growth;     // source S(x, t) = exp(growth t) S0(x)
+    bool gen;          // general node model: a power-law flux or a phi-dependent source
 };
 
 int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
@@ -68,6 +70,14 @@ struct Instance {
     bool k1_per_node = false;
     bool afield = false;  // per-node A0(x) planes in the workspace
     double growth = 0.0;  // source growth rate per step (Scheme 2 correction when nonzero)
+    // General node model (kGen): wall table entries of 2 (nx + ny) values in the phi type; the
+    // pull at step count t reads entry (t - wall_t0) at wtab + (t - wall_t0) * wall_stride. Steps
+    // may advance the count up to wall_limit.
+    bool gen = false;
+    const char* wtab = nullptr;
+    int64_t wall_t0 = 0;
+    int64_t wall_limit = INT64_MAX;
+    int wall_stride = 0;
     int perx = 1, pery = 1;
     int64_t plane = 0;
     double wall[4] = {0, 0, 0, 0};
@@ -79,7 +89,12 @@ struct Instance {
     SweepArgs<double> a64{};  // problem constants; buffer pointers are set per launch
     SweepArgs<float> a32{};
     btrt_info_t info{};
-    int kmode() const { return afield ? btrtk::kK1Field : (k1_per_node ? btrtk::kK1Phi : btrtk::kK1Const); }
+    int kmode() const
+    {
+        const int k1 = afield ? btrtk::kK1Field : (k1_per_node ? btrtk::kK1Phi : btrtk::kK1Const);
+        return gen ? (k1 | btrtk::kGen) : k1;
+    }
+    int wall_entry_values() const { return 2 * (nx + ny); }
 };
 
 // Places a validated problem into mem (at least layout_for(...).total bytes, 256-byte
@@ -88,6 +103,12 @@ struct Instance {
 int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,
                    const btrt_source_t* R, const btrt_bc_t* bc, const Resolved& r, const double* phi0, char* mem,
                    hipStream_t s);
+
+// Wall-table entry of the per-side constants (2 (nx + ny) values, see Instance).
+std::vector<double> wall_entry_constants(const Instance& I);
+// Copies count FP64 wall values to device memory dst in I's phi type; synchronises s.
+hipError_t upload_wall_values(const Instance& I, const double* v, size_t count, char* dst, hipStream_t s);
+hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s);
 
 // Sweep arguments with the buffer pointers for the given parity (0: f[0] -> f[1]).
 template <typename T>

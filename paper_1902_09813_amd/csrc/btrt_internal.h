@@ -18,6 +18,11 @@ enum ReduceMode : int { kResidual = 0, kError = 1 };
 // How the kernels obtain K1 (Eq. (30)): the constant of the problem, or per node from
 // A0 (1 + beta phi^2), or per node from a space-dependent A0(x) (1 + beta phi^2).
 enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
+// Kernel mode = K1 mode | kGen. kGen selects the general node model: a power-law flux term
+// c |phi|^q, a source part r phi (1 - |phi|^p) that depends on phi, and Dirichlet values read
+// per boundary node and step from a wall table.
+constexpr int kK1Mask = 3;
+constexpr int kGen = 4;
 
 constexpr int kMaxFuse = 4;  // most time steps one sweep launch can fuse
 
@@ -40,6 +45,12 @@ struct SweepArgs {
     T k0, k2xx, k2xy, k2yy;
     T src_amp;
     T sfac[kMaxFuse];  // source factor of each step of the launch (1: time independent)
+    T fcx, fcy, fq;    // kGen: B(phi) gains (fcx, fcy) |phi|^fq
+    T rr, rp;          // kGen: the source gains rr phi (1 - |phi|^rp)
+    const T* wtab;     // wall table (kGen, else null): entry e holds the Dirichlet values of the
+                       // pull at step e of the launch at wtab + e * wstride: x- (ny, by row),
+                       // x+ (ny), y- (nx, by column), y+ (nx)
+    int wstride;       // elements between entries (0: one entry for every step)
     const T* afield;   // kK1Field: three planes a11, a12, a22 (plane stride `plane`)
     T dev_scale, dev_inv; // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq)), f+ = f_eq + h dev_inv
     int tiles_x, tiles_y; // set by the launcher for the kernel it picks
@@ -97,9 +108,10 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode,
 template <typename T>
 LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, LaunchCfg cfg);
 // f+(-1) and phi(-1) := phi0 into a.fin / a.phi_prev (see init_values); FP64 arithmetic.
+// The flux of the init is B(phi) = a phi + b phi^2 / 2 + c |phi|^q (c = 0: no power-law term).
 template <typename T>
-hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,
-                       double bx, double by, hipStream_t s);
+hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], const double ab[4],
+                       const double cq[3], hipStream_t s);
 template <typename T>
 hipError_t launch_gather_field(const GatherArgs<T>& a, int fmt, hipStream_t s);
 template <typename T>

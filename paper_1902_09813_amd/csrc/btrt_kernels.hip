@@ -11,19 +11,23 @@ namespace {
 
 // f+(-1) such that the first pull yields f(0) = f^eq(phi0) (Section 4 initialisation), and
 // phi(-1) := phi0; written through the format's put into a.fout / a.phi_out.
+struct InitConsts {
+    double wall[4];
+    double ab[4];  // ax, ay, bx, by
+    double cq[3];  // cx, cy, q
+};
+
 template <typename F>
 __global__ __launch_bounds__(kBlock) void init_kernel(SweepArgs<typename F::T> a, const double* __restrict__ phi0,
-                                                      double w0, double w1, double w2, double w3, double ax,
-                                                      double ay, double bx, double by)
+                                                      InitConsts c)
 {
     using T = typename F::T;
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (k >= static_cast<int64_t>(a.nx) * a.ny) return;
     const int y = static_cast<int>(k / a.nx);
     const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.nx);
-    const double wall[4] = {w0, w1, w2, w3};
     T f[9];
-    init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, wall, ax, ay, bx, by,
+    init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, c.wall, c.ab, c.cq,
                 [&](int i, double v) { f[i] = static_cast<T>(v); });
     F::put(a, y * a.pitch + x, f, static_cast<T>(phi0[k]));
 }
@@ -145,12 +149,15 @@ __global__ __launch_bounds__(kBlock) void reduce_final_kernel(const double* __re
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
 template <typename F>
-hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], double ax, double ay,
-                     double bx, double by, hipStream_t s)
+hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], const double ab[4],
+                     const double cq[3], hipStream_t s)
 {
     const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
-    hipLaunchKernelGGL((init_kernel<F>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a, phi0, wall[0], wall[1], wall[2],
-                       wall[3], ax, ay, bx, by);
+    InitConsts c{};
+    for (int q = 0; q < 4; ++q) c.wall[q] = wall[q];
+    for (int q = 0; q < 4; ++q) c.ab[q] = ab[q];
+    for (int q = 0; q < 3; ++q) c.cq[q] = cq[q];
+    hipLaunchKernelGGL((init_kernel<F>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a, phi0, c);
     return hipGetLastError();
 }
 
@@ -196,6 +203,13 @@ template <typename T>
 hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, const LaunchCfg& cfg,
                         hipStream_t s)
 {
+    if ((kmode & kGen) != 0) {  // the general node model: plain storage only
+        if (fmt != kFmtPlain) return hipErrorInvalidValue;
+        if constexpr (sizeof(T) == 8)
+            return sweep_gen_f64(a, src_kind, kmode, cfg, s);
+        else
+            return sweep_gen_f32(a, src_kind, kmode, cfg, s);
+    }
     if constexpr (sizeof(T) == 8) {
         if (fmt != kFmtPlain) return hipErrorInvalidValue;
         return sweep_f64(a, src_kind, kmode, cfg, s);
@@ -209,6 +223,12 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode,
 template <typename T>
 LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, LaunchCfg cfg)
 {
+    if ((kmode & kGen) != 0) {
+        if constexpr (sizeof(T) == 8)
+            return resolve_gen_f64(a, src_kind, kmode, cfg);
+        else
+            return resolve_gen_f32(a, src_kind, kmode, cfg);
+    }
     if constexpr (sizeof(T) == 8) {
         return resolve_f64(a, src_kind, kmode, cfg);
     } else {
@@ -219,10 +239,10 @@ LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode
 }
 
 template <typename T>
-hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], double ax, double ay,
-                       double bx, double by, hipStream_t s)
+hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], const double ab[4],
+                       const double cq[3], hipStream_t s)
 {
-    BTRT_BY_FORMAT(T, init_with, a, phi0, wall, ax, ay, bx, by, s);
+    BTRT_BY_FORMAT(T, init_with, a, phi0, wall, ab, cq, s);
 }
 
 template <typename T>
@@ -250,8 +270,8 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
 #define BTRT_INSTANTIATE(T)                                                                                        \
     template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, int, const LaunchCfg&, hipStream_t);       \
     template LaunchCfg resolve_launch<T>(const SweepArgs<T>&, int, int, int, LaunchCfg);                         \
-    template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], double, double,   \
-                                       double, double, hipStream_t);                                               \
+    template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], const double[4],  \
+                                       const double[3], hipStream_t);                                              \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, int, hipStream_t);                           \
     template hipError_t launch_reduce<T>(const GatherArgs<T>&, int, int, double*, hipStream_t);                   \
     template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);                         \

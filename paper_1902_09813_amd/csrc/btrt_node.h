@@ -18,6 +18,16 @@ __host__ __device__ inline T fmadd(T a, T b, T c)
         return fma(a, b, c);
 }
 
+// |x|^y in the storage type (the power-law flux and the phi-dependent source).
+template <typename T>
+__host__ __device__ inline T abspow(T x, T y)
+{
+    if constexpr (sizeof(T) == 4)
+        return powf(fabsf(x), y);
+    else
+        return pow(fabs(x), y);
+}
+
 // Half-way bounce-back value (Eqs. (54)-(56)): -f_opp+ + 2 w phi_w.
 template <typename T>
 __host__ __device__ inline T bounce(T f_opp, T two_w, T phi_w)
@@ -37,6 +47,18 @@ __host__ __device__ inline T wall_value(bool out_x, bool out_y, T vx, T vy)
 {
     // A link crossing both walls (a corner point) takes the mean of the two values.
     return (out_x && out_y) ? T(0.5) * (vx + vy) : (out_x ? vx : vy);
+}
+
+// Dirichlet values of node (x, y) at step lvl of a launch from the wall table: side x- and x+
+// at the node's row, y- and y+ at its column.
+template <typename T>
+__host__ __device__ inline void table_walls(const SweepArgs<T>& a, int x, int y, int lvl, T w[4])
+{
+    const T* e = a.wtab + lvl * a.wstride;
+    w[0] = e[y];
+    w[1] = e[a.ny + y];
+    w[2] = e[2 * a.ny + x];
+    w[3] = e[2 * a.ny + a.nx + x];
 }
 
 // Pull f_i(x, t) for all nine directions: load(i, idx) returns the post-collision value
@@ -117,11 +139,14 @@ __host__ __device__ inline T sum9(const T f[9])
 // f+(x, t) on return. Returns phi(t). The library is built without floating-point
 // contraction: every fused multiply-add below is written out, so a node update rounds the
 // same way in every kernel that inlines it.
-// KM (K1Mode) selects where K1 comes from; n is the node's in-plane index (read only for an
-// A0 field). s is the source term of the step, with the Scheme 2 correction folded in.
+// KM (K1Mode, plus kGen) selects where K1 comes from and the node model; n is the node's
+// in-plane index (read only for an A0 field). s is the part of the source term of the step that
+// does not depend on phi, with the Scheme 2 correction folded in.
 template <typename T, int SRC, int KM>
 __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, T s, int n)
 {
+    constexpr int K1M = KM & kK1Mask;
+    constexpr bool GEN = (KM & kGen) != 0;
     constexpr T third = T(1) / T(3);
     constexpr T sixth = T(1) / T(6);
     constexpr T twelfth = T(1) / T(12);
@@ -143,17 +168,36 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     // Flux B(phi) = phi (a + b phi / 2) and its backward difference over one step (the
     // correction G of Eq. (11)).
     const T hbx = half * a.bx, hby = half * a.by;
-    const T Bx = phi * fmadd(hbx, phi, a.ax);
-    const T By = phi * fmadd(hby, phi, a.ay);
-    const T dBx = fmadd(-phi_prev, fmadd(hbx, phi_prev, a.ax), Bx);
-    const T dBy = fmadd(-phi_prev, fmadd(hby, phi_prev, a.ay), By);
+    T Bx = phi * fmadd(hbx, phi, a.ax);
+    T By = phi * fmadd(hby, phi, a.ay);
+    T dBx, dBy;
+    if (GEN && (a.fcx != T(0) || a.fcy != T(0))) {
+        // General model: B gains c |phi|^q.
+        const T pw = abspow(phi, a.fq), pwp = abspow(phi_prev, a.fq);
+        const T Bxp = fmadd(a.fcx, pwp, phi_prev * fmadd(hbx, phi_prev, a.ax));
+        const T Byp = fmadd(a.fcy, pwp, phi_prev * fmadd(hby, phi_prev, a.ay));
+        Bx = fmadd(a.fcx, pw, Bx);
+        By = fmadd(a.fcy, pw, By);
+        dBx = Bx - Bxp;
+        dBy = By - Byp;
+    } else {
+        dBx = fmadd(-phi_prev, fmadd(hbx, phi_prev, a.ax), Bx);
+        dBy = fmadd(-phi_prev, fmadd(hby, phi_prev, a.ay), By);
+    }
+    if (GEN && a.rr != T(0)) {
+        // General model: S(phi) = r phi (1 - |phi|^p) with the Scheme 2 correction,
+        // S(t) + (S(t) - S(t-1))/2, S(t-1) taken at phi(t-1).
+        const T R = (a.rr * phi) * (T(1) - abspow(phi, a.rp));
+        const T Rp = (a.rr * phi_prev) * (T(1) - abspow(phi_prev, a.rp));
+        s = s + fmadd(T(1.5), R, -half * Rp);
+    }
 
     // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)), per node when A depends on phi or on x
     // (A = A0(x) (1 + beta phi^2), Eq. (73)).
     T K11 = a.K11, K12 = a.K12, K22 = a.K22;
-    if constexpr (KM != kK1Const) {
+    if constexpr (K1M != kK1Const) {
         T a11 = a.a11, a12 = a.a12, a22 = a.a22;
-        if constexpr (KM == kK1Field) {
+        if constexpr (K1M == kK1Field) {
             a11 = a.afield[n];
             a12 = a.afield[a.plane + n];
             a22 = a.afield[2 * a.plane + n];
@@ -213,11 +257,23 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
 // f+(-1) at node (x, y) such that the first pull yields f(0) = f^eq(phi0) (Section 4): a value
 // whose consumer is an interior pull gets f^eq of Eq. (7) (D = phi I) at its destination; a
 // value whose consumer is the bounce-back rule gets 2 w phi_w - f^eq_opp at its own node.
+// ab = (ax, ay, bx, by), cq = (cx, cy, q): B(phi) = a phi + b phi^2 / 2 + c |phi|^q.
 // put(i, v) receives the value for direction i (FP64).
+__host__ __device__ inline void init_flux(double p, const double ab[4], const double cq[3], double& Bx, double& By)
+{
+    Bx = p * (ab[0] + 0.5 * ab[2] * p);
+    By = p * (ab[1] + 0.5 * ab[3] * p);
+    if (cq[0] != 0.0 || cq[1] != 0.0) {
+        const double pw = pow(fabs(p), cq[2]);
+        Bx += cq[0] * pw;
+        By += cq[1] * pw;
+    }
+}
+
 template <typename Put>
 __host__ __device__ inline void init_values(const double* __restrict__ phi0, int x, int y, int nx, int ny, int perx,
-                                            int pery, const double wall[4], double ax, double ay, double bx,
-                                            double by, Put put)
+                                            int pery, const double wall[4], const double ab[4], const double cq[3],
+                                            Put put)
 {
     constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -234,7 +290,8 @@ __host__ __device__ inline void init_values(const double* __restrict__ phi0, int
         double v;
         if (!outx && !outy) {
             const double p = phi0[static_cast<int64_t>(yd) * nx + xd];
-            const double Bx = p * (ax + 0.5 * bx * p), By = p * (ay + 0.5 * by * p);
+            double Bx, By;
+            init_flux(p, ab, cq, Bx, By);
             v = wt[i] * (p + 3.0 * (cx[i] * Bx + cy[i] * By));
         } else {
             // The link leaves through x- or x+ (y- or y+) according to the sign of c_i.
@@ -242,7 +299,8 @@ __host__ __device__ inline void init_values(const double* __restrict__ phi0, int
             const double vy = wall[cy[i] < 0 ? 2 : 3];
             const double pw = (outx && outy) ? 0.5 * (vx + vy) : (outx ? vx : vy);
             const int o = opp[i];
-            const double Bx = here * (ax + 0.5 * bx * here), By = here * (ay + 0.5 * by * here);
+            double Bx, By;
+            init_flux(here, ab, cq, Bx, By);
             const double feq_o = wt[o] * (here + 3.0 * (cx[o] * Bx + cy[o] * By));
             v = 2.0 * wt[i] * pw - feq_o;
         }

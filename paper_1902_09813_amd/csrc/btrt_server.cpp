@@ -244,8 +244,9 @@ int btrt_server_submit(btrt_server_t* s, const btrt_problem_t* p, double tol, in
     if (rc == BTRT_OK) rc = validate_phi0(&p->grid, p->phi0);
     if (rc != BTRT_OK) return rc;
     if (p->grid.precision != s->precision) return fail(BTRT_E_INVAL, "request precision differs from the server's");
-    if (r->res.afield || r->res.growth != 0.0)
-        return fail(BTRT_E_INVAL, "served requests take no A0 field and no growing source");
+    if (r->res.afield || r->res.growth != 0.0 || r->res.gen)
+        return fail(BTRT_E_INVAL,
+                    "served requests take no A0 field, growing source, power-law flux or phi-dependent source");
     r->bytes = layout_for(p->grid.nx, p->grid.ny, s->precision, p->R.kind).total;
     if (align_up(r->bytes) > s->mem_bytes)
         return fail(BTRT_E_NOMEM, "request needs %zu bytes, server has %zu", r->bytes, s->mem_bytes);

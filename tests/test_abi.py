@@ -119,3 +119,28 @@ def test_space_dependent_tensor_and_growing_source_reach_the_library():
     assert "node 53" in msg
     _expect_inval(btrt.Problem(16, 16, A0_field=w.A0_field, k2="hbb"))
     _expect_inval(btrt.Problem(16, 16, A0=(0.01, 0.0, 0.01), source=("field", w.source[1], np.inf)))
+
+
+def test_general_model_parameters_reach_the_library():
+    # The power-law flux and the phi-dependent source of the Burgers-Fisher problem (Eq. (67))
+    # pass validation with plain storage, and their exponents and storage formats are checked
+    # on the host.
+    w = W.bfe(n=20)
+    p = btrt.problem_from_workload(w)
+    info = p.validate()
+    k1 = 1.0 / (3 * w.A0[0] + 0.5)
+    assert info.K1[0] == pytest.approx(k1, rel=1e-15)
+    assert info.K2[0] == pytest.approx(8 * (k1 - 2) / (3 * (k1 - 4)), rel=1e-14)
+    assert (p.flux.c[0], p.flux.q, p.source.r, p.source.p) == (w.flux_c[0], w.flux_q, w.src_r, w.src_p)
+    btrt.problem_from_workload(w, precision=btrt.F32).validate()
+    good = dict(A0=(0.01, 0.0, 0.01))
+    assert "exponent q" in _expect_inval(btrt.Problem(4, 4, flux_c=(0.1, 0.0), flux_q=0.5, **good))
+    _expect_inval(btrt.Problem(4, 4, flux_c=(0.1, 0.0), flux_q=np.nan, **good))
+    _expect_inval(btrt.Problem(4, 4, flux_c=(np.inf, 0.0), flux_q=2.0, **good))
+    assert "exponent p" in _expect_inval(btrt.Problem(4, 4, src_r=0.01, src_p=0.0, **good))
+    _expect_inval(btrt.Problem(4, 4, src_r=np.nan, **good))
+    for prec in (btrt.F16DEV, btrt.BF16DEV):
+        assert "BTRT_F64 or BTRT_F32" in _expect_inval(btrt.Problem(4, 4, precision=prec, src_r=0.01, **good))
+        _expect_inval(btrt.Problem(4, 4, precision=prec, flux_c=(0.1, 0.0), flux_q=2.0, **good))
+    # Exponents are read only where their term is present.
+    btrt.Problem(4, 4, flux_q=0.0, src_p=-1.0, **good).validate()
