@@ -45,6 +45,17 @@ static void flux(const orc_problem_t* p, double phi, double B[2])
     }
 }
 
+/* The tensor D(phi) of Eq. (1), as it enters the equilibrium of Eq. (7). */
+static void dterm(const orc_problem_t* p, double phi, double D[4])
+{
+    double d = phi;
+    if (p->d_kind == 1) d = p->d_g * phi + p->d_e * pow(fabs(phi), p->d_s);
+    D[0] = d;
+    D[1] = 0.0;
+    D[2] = 0.0;
+    D[3] = d;
+}
+
 /* The phi-dependent part of S(x, phi, t) in Eq. (1): r phi (1 - |phi|^p). */
 static double reaction(const orc_problem_t* p, double phi)
 {
@@ -103,8 +114,8 @@ static void collide_with(const orc_problem_t* p, const double A0[3], const doubl
     /* S(x, phi, t): the given part plus the phi-dependent one, at t and at t-1 (Scheme 2). */
     S += reaction(p, phi);
     S_prev += reaction(p, phi_prev);
-    /* D = phi I for every problem this project runs. */
-    double D[4] = {phi, 0.0, 0.0, phi};
+    double D[4];
+    dterm(p, phi, D);
     double g = 1.0 + p->beta * phi * phi;
     double A[4] = {A0[0] * g, A0[1] * g, A0[1] * g, A0[2] * g};
     double K1[4];
@@ -163,7 +174,8 @@ void orc_init(const orc_problem_t* p, const double* phi0, double* f)
     for (long k = 0; k < n; ++k) {
         double B[2];
         flux(p, phi0[k], B);
-        double D[4] = {phi0[k], 0.0, 0.0, phi0[k]};
+        double D[4];
+        dterm(p, phi0[k], D);
         double feq[9];
         orc_equilibrium(phi0[k], B, D, feq);
         for (int i = 0; i < 9; ++i) f[i * n + k] = feq[i];

@@ -52,6 +52,10 @@ typedef struct {
      * with r = b, p = delta). Ignored when src_r is 0. */
     double src_r;
     double src_p;
+    /* D(phi) of Eq. (1) and Eq. (7): d_kind 0 is D = phi I; d_kind 1 is
+     * D = (d_g phi + d_e |phi|^d_s) I. */
+    int d_kind;
+    double d_g, d_e, d_s;
 } orc_problem_t;
 
 /* D2Q9 equilibrium of Eq. (7) for a general D tensor (row major 2x2). */

@@ -50,6 +50,10 @@ class _CProblem(ctypes.Structure):
         ("flux_q", ctypes.c_double),
         ("src_r", ctypes.c_double),
         ("src_p", ctypes.c_double),
+        ("d_kind", ctypes.c_int),
+        ("d_g", ctypes.c_double),
+        ("d_e", ctypes.c_double),
+        ("d_s", ctypes.c_double),
     ]
 
 
@@ -98,6 +102,7 @@ class Problem:
     k0, K2: relaxation of the S0 block and the 2x2 K2 block of Eq. (6) (row major).
     bc_type/bc_value: sides x-, x+, y-, y+.
     src_r, src_p: phi-dependent source r phi (1 - |phi|^p), added to any given S.
+    dterm: None for D = phi I, or (g, e, s) for D = (g phi + e |phi|^s) I (Eq. (1), Eq. (7)).
     """
 
     nx: int
@@ -115,6 +120,7 @@ class Problem:
     flux_q: float = 1.0
     src_r: float = 0.0
     src_p: float = 1.0
+    dterm: Optional[Sequence[float]] = None
 
     def c(self) -> _CProblem:
         p = _CProblem()
@@ -134,6 +140,9 @@ class Problem:
         p.flux_q = float(self.flux_q)
         p.src_r = float(self.src_r)
         p.src_p = float(self.src_p)
+        if self.dterm is not None:
+            p.d_kind = 1
+            p.d_g, p.d_e, p.d_s = (float(v) for v in self.dterm)
         if self.A0_field is not None:
             field = np.ascontiguousarray(self.A0_field, dtype=np.float64)
             assert field.shape == (self.ny, self.nx, 3)

@@ -79,6 +79,7 @@ class Workload:
     src_p: float = 1.0
     walls: Optional[Callable[[int], np.ndarray]] = None  # k -> Dirichlet values of the k-th step
     #                                         along the sides: x- (ny), x+ (ny), y- (nx), y+ (nx)
+    dterm: Optional[Tuple[float, float, float]] = None  # D = (g phi + e |phi|^s) I; None: D = phi I
 
     def phi0(self) -> np.ndarray:
         return initial_field(self)

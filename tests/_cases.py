@@ -18,7 +18,7 @@ def oracle_problem(w) -> "O.Problem":
         k2 = tuple(w.k2)
     return O.Problem(w.nx, w.ny, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta, k0=w.k0, K2=k2,
                      bc_type=w.bc_type, bc_value=w.bc_value, A0_field=getattr(w, "A0_field", None),
-                     flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p)
+                     flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p, dterm=w.dterm)
 
 
 def oracle_source(w):
