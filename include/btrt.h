@@ -64,7 +64,8 @@ extern "C" {
 #define BTRT_SRC_FIELD 1 /* S(x) given per node */
 #define BTRT_SRC_SIN 2   /* S = amp sin(kx pi x / nx) sin(ky pi y / ny) at cell centres */
 
-#define BTRT_D_PHI_I 0   /* D(phi) = phi I, the only D the library accepts */
+#define BTRT_D_PHI_I 0   /* D(phi) = phi I */
+#define BTRT_D_POLY 1    /* D(phi) = (g phi + e |phi|^s) I */
 
 #define BTRT_K2_VALUE 0  /* K2 given explicitly (relax.k2) */
 #define BTRT_K2_HBB 1    /* k2 = 8(k1-2)/(3(k1-4)), Eq. (62); needs A = alpha I constant */
@@ -105,8 +106,13 @@ typedef struct {
     const double* field;
 } btrt_diff_t;
 
+/* D(phi) of Eq. (1), through the equilibrium of Eq. (7) (whose second moment is c_s^2 D, Eq. (9)):
+ * phi I, or (g phi + e |phi|^s) I. s is read only when e != 0 and must then be >= 1. The
+ * equilibrium rest population is w_0 (2 phi - d), so the scheme needs d(phi) < 2 phi where phi > 0.
+ * BTRT_D_POLY selects the general node model (BTRT_F64 or BTRT_F32 storage, single handles only). */
 typedef struct {
-    int32_t kind; /* BTRT_D_PHI_I */
+    int32_t kind; /* BTRT_D_PHI_I or BTRT_D_POLY */
+    double g, e, s;
 } btrt_dterm_t;
 
 /* Source S of Eq. (8): S(x, phi, t) = exp(growth * t) * S0(x) + r*phi*(1 - |phi|^p) at step t
@@ -163,7 +169,8 @@ typedef struct {
 /* Checks a problem and fills *info (optional) without touching any device.
  * Errors: BTRT_E_INVAL for sizes out of range, unpaired periodic sides, A (or any node of an
  * A0 field) not SPD or beta < 0, rates outside (0, 2), a power-law exponent q < 1 or a
- * reaction exponent p <= 0 where used, the general node model with BTRT_F16DEV or
+ * reaction exponent p <= 0 where used, a D exponent s < 1 where used, the general node model
+ * (a power-law flux, a phi-dependent source or BTRT_D_POLY) with BTRT_F16DEV or
  * BTRT_BF16DEV, BTRT_K2_HBB with a non-isotropic,
  * phi-dependent or space-dependent A, an unsupported D or source kind, or non-finite values. */
 int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K,

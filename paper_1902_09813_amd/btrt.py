@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, 1, 2, 3, 4, 5
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, DIRICHLET = 0, 1
 SRC_NONE, SRC_FIELD, SRC_SIN = 0, 1, 2
-D_PHI_I = 0
+D_PHI_I, D_POLY = 0, 1
 K2_VALUE, K2_HBB = 0, 1
 
 # Every function include/btrt.h declares.
@@ -53,7 +53,7 @@ class Diff(ctypes.Structure):
 
 
 class DTerm(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32)]
+    _fields_ = [("kind", ctypes.c_int32), ("g", ctypes.c_double), ("e", ctypes.c_double), ("s", ctypes.c_double)]
 
 
 class Source(ctypes.Structure):
@@ -217,14 +217,15 @@ class Problem:
     beta: A = A0 (1 + beta phi^2); A0_field: None or an (ny, nx, 3) array of per-node
     (a11, a12, a22) replacing A0; source: None, an (ny, nx) array, ("sin", amp, kx, ky) or
     ("field", array, growth) for S(x, t) = exp(growth t) array(x); src_r, src_p: the source gains
-    r phi (1 - |phi|^p); bc_type/bc_value for sides x-, x+, y-, y+; k0; k2: "hbb" (Eq. (62)), a
-    scalar (K2 = k2 Ihat) or four entries.
+    r phi (1 - |phi|^p); dterm: None (D = phi I) or (g, e, s) for D = (g phi + e |phi|^s) I;
+    bc_type/bc_value for sides x-, x+, y-, y+; k0; k2: "hbb" (Eq. (62)), a scalar (K2 = k2 Ihat)
+    or four entries.
     """
 
     def __init__(self, nx: int, ny: int, *, precision: int = F64, flux_a=(0.0, 0.0), flux_b=(0.0, 0.0),
                  A0=(0.0, 0.0, 0.0), beta: float = 0.0, A0_field=None, source=None, bc_type=(PERIODIC,) * 4,
                  bc_value=(0.0,) * 4, k0: float = 1.0, k2=1.0, check_interval: int = 1000, device: int = 0,
-                 flux_c=(0.0, 0.0), flux_q: float = 1.0, src_r: float = 0.0, src_p: float = 1.0):
+                 flux_c=(0.0, 0.0), flux_q: float = 1.0, src_r: float = 0.0, src_p: float = 1.0, dterm=None):
         self.grid = Grid(int(nx), int(ny), int(precision), int(device), None, None, 0)
         self.flux = Flux((ctypes.c_double * 2)(*flux_a), (ctypes.c_double * 2)(*flux_b),
                          (ctypes.c_double * 2)(*flux_c), float(flux_q))
@@ -233,7 +234,7 @@ class Problem:
             self._afield = np.ascontiguousarray(A0_field, dtype=np.float64).reshape(ny, nx, 3)
         self.diff = Diff(float(A0[0]), float(A0[1]), float(A0[2]), float(beta),
                          _dptr(self._afield) if self._afield is not None else None)
-        self.dterm = DTerm(D_PHI_I)
+        self.dterm = DTerm(D_PHI_I, 1.0, 0.0, 1.0) if dterm is None else DTerm(D_POLY, *(float(v) for v in dterm))
         self._field = None
         if source is None:
             self.source = Source(SRC_NONE, 0.0, 0, 0, None, 0.0, 0.0, 1.0)
@@ -405,7 +406,7 @@ def problem_from_workload(w, precision: int = F64, device: int = 0, check_interv
     return Problem(w.nx, w.ny, precision=precision, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta,
                    A0_field=getattr(w, "A0_field", None), source=w.source, bc_type=w.bc_type,
                    bc_value=w.bc_value, k0=w.k0, k2=w.k2, check_interval=check_interval, device=device,
-                   flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p)
+                   flux_c=w.flux_c, flux_q=w.flux_q, src_r=w.src_r, src_p=w.src_p, dterm=w.dterm)
 
 
 def wall_schedule(w, start: int, steps: int) -> np.ndarray:

@@ -149,7 +149,16 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
                         K->k12, K->k22);
     }
     if (K->beta < 0.0) return fail(BTRT_E_INVAL, "beta = %g < 0", K->beta);
-    if (D->kind != BTRT_D_PHI_I) return fail(BTRT_E_INVAL, "D kind %d: only D = phi I is supported", D->kind);
+    if (D->kind != BTRT_D_PHI_I && D->kind != BTRT_D_POLY)
+        return fail(BTRT_E_INVAL, "D kind %d: not BTRT_D_PHI_I or BTRT_D_POLY", D->kind);
+    const bool dpoly = D->kind == BTRT_D_POLY;
+    if (dpoly) {
+        if (!is_finite(D->g) || !is_finite(D->e)) return fail(BTRT_E_INVAL, "non-finite D coefficient");
+        if (D->e != 0.0 && !(is_finite(D->s) && D->s >= 1.0))
+            return fail(BTRT_E_INVAL, "D exponent s = %g: must be finite and >= 1", D->s);
+        if (grid->precision != BTRT_F64 && grid->precision != BTRT_F32)
+            return fail(BTRT_E_INVAL, "D other than phi I needs BTRT_F64 or BTRT_F32 storage");
+    }
     for (int s = 0; s < 4; ++s) {
         if (bc->type[s] != BTRT_PERIODIC && bc->type[s] != BTRT_DIRICHLET)
             return fail(BTRT_E_INVAL, "side %d: boundary type %d", s, bc->type[s]);
@@ -188,7 +197,11 @@ int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K
     res->afield = K->field != nullptr;
     res->k1_per_node = K->beta != 0.0 || res->afield;
     res->growth = R && R->kind != BTRT_SRC_NONE ? R->growth : 0.0;
-    res->gen = power || reaction;
+    res->gen = power || reaction || dpoly;
+    res->dq[0] = dpoly ? 1.0 : 0.0;
+    res->dq[1] = dpoly ? D->g : 1.0;
+    res->dq[2] = dpoly ? D->e : 0.0;
+    res->dq[3] = dpoly && D->e != 0.0 ? D->s : 1.0;
 
     if (relax->k2_rule == BTRT_K2_HBB) {
         // Eq. (62) removes the bounce-back slip for K1 = k1 I (Section 3).
@@ -293,6 +306,10 @@ void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const bt
     a.fq = static_cast<T>(B->c[0] != 0.0 || B->c[1] != 0.0 ? B->q : 1.0);
     a.rr = static_cast<T>(R ? R->r : 0.0);
     a.rp = static_cast<T>(R && R->r != 0.0 ? R->p : 1.0);
+    a.dpoly = r.dq[0] != 0.0 ? 1 : 0;
+    a.dg = static_cast<T>(r.dq[1]);
+    a.de = static_cast<T>(r.dq[2]);
+    a.ds = static_cast<T>(r.dq[3]);
     a.wtab = nullptr;  // set per launch (sweep_args) for the general node model
     a.wstride = 0;
     // Non-temporal stores once the two buffers of populations and phi exceed the 256 MB
@@ -414,9 +431,9 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
     const double ab[4] = {B->a[0], B->a[1], B->b[0], B->b[1]};
     const double cq[3] = {B->c[0], B->c[1], B->c[0] != 0.0 || B->c[1] != 0.0 ? B->q : 1.0};
     if (I.precision == BTRT_F64)
-        err = launch_init<double>(sweep_args<double>(I, 1), kFmtPlain, tmp, I.wall, ab, cq, s);
+        err = launch_init<double>(sweep_args<double>(I, 1), kFmtPlain, tmp, I.wall, ab, cq, r.dq, s);
     else
-        err = launch_init<float>(sweep_args<float>(I, 1), format_of(I.precision), tmp, I.wall, ab, cq, s);
+        err = launch_init<float>(sweep_args<float>(I, 1), format_of(I.precision), tmp, I.wall, ab, cq, r.dq, s);
     if (err != hipSuccess) return hip_fail(err, "init launch");
     err = hipMemcpyAsync(mem + I.L.snap, tmp, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (err != hipSuccess) return hip_fail(err, "snapshot copy");

@@ -52,7 +52,8 @@ struct Resolved {
     bool k1_per_node;  // beta > 0 or a per-node A0(x)
     bool afield;       // A0(x) given per node
     double growth;     // source S(x, t) = exp(growth t) S0(x)
-    bool gen;          // general node model: a power-law flux or a phi-dependent source
+    bool gen;          // general node model: a power-law flux, a phi-dependent source or D != phi I
+    double dq[4];      // D(phi): (0, ...) phi I; (1, g, e, s) (g phi + e |phi|^s) I
 };
 
 int validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,

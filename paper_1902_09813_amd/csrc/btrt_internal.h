@@ -47,6 +47,8 @@ struct SweepArgs {
     T sfac[kMaxFuse];  // source factor of each step of the launch (1: time independent)
     T fcx, fcy, fq;    // kGen: B(phi) gains (fcx, fcy) |phi|^fq
     T rr, rp;          // kGen: the source gains rr phi (1 - |phi|^rp)
+    T dg, de, ds;      // kGen with dpoly: D(phi) = (dg phi + de |phi|^ds) I
+    int dpoly;
     const T* wtab;     // wall table (kGen, else null): entry e holds the Dirichlet values of the
                        // pull at step e of the launch at wtab + e * wstride: x- (ny, by row),
                        // x+ (ny), y- (nx, by column), y+ (nx)
@@ -108,10 +110,11 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode,
 template <typename T>
 LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode, LaunchCfg cfg);
 // f+(-1) and phi(-1) := phi0 into a.fin / a.phi_prev (see init_values); FP64 arithmetic.
-// The flux of the init is B(phi) = a phi + b phi^2 / 2 + c |phi|^q (c = 0: no power-law term).
+// The flux of the init is B(phi) = a phi + b phi^2 / 2 + c |phi|^q (c = 0: no power-law term);
+// D(phi) = phi I, or (g phi + e |phi|^s) I when dq = (1, g, e, s).
 template <typename T>
 hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], const double ab[4],
-                       const double cq[3], hipStream_t s);
+                       const double cq[3], const double dq[4], hipStream_t s);
 template <typename T>
 hipError_t launch_gather_field(const GatherArgs<T>& a, int fmt, hipStream_t s);
 template <typename T>

@@ -15,6 +15,7 @@ struct InitConsts {
     double wall[4];
     double ab[4];  // ax, ay, bx, by
     double cq[3];  // cx, cy, q
+    double dq[4];  // D kind, g, e, s
 };
 
 template <typename F>
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(SweepArgs<typename F::T> a
     const int y = static_cast<int>(k / a.nx);
     const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.nx);
     T f[9];
-    init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, c.wall, c.ab, c.cq,
+    init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, c.wall, c.ab, c.cq, c.dq,
                 [&](int i, double v) { f[i] = static_cast<T>(v); });
     F::put(a, y * a.pitch + x, f, static_cast<T>(phi0[k]));
 }
@@ -150,13 +151,14 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock
 
 template <typename F>
 hipError_t init_with(const SweepArgs<typename F::T>& a, const double* phi0, const double wall[4], const double ab[4],
-                     const double cq[3], hipStream_t s)
+                     const double cq[3], const double dq[4], hipStream_t s)
 {
     const int64_t nn = static_cast<int64_t>(a.nx) * a.ny;
     InitConsts c{};
     for (int q = 0; q < 4; ++q) c.wall[q] = wall[q];
     for (int q = 0; q < 4; ++q) c.ab[q] = ab[q];
     for (int q = 0; q < 3; ++q) c.cq[q] = cq[q];
+    for (int q = 0; q < 4; ++q) c.dq[q] = dq[q];
     hipLaunchKernelGGL((init_kernel<F>), dim3(blocks_for(nn)), dim3(kBlock), 0, s, a, phi0, c);
     return hipGetLastError();
 }
@@ -240,9 +242,9 @@ LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode
 
 template <typename T>
 hipError_t launch_init(const SweepArgs<T>& a, int fmt, const double* phi0, const double wall[4], const double ab[4],
-                       const double cq[3], hipStream_t s)
+                       const double cq[3], const double dq[4], hipStream_t s)
 {
-    BTRT_BY_FORMAT(T, init_with, a, phi0, wall, ab, cq, s);
+    BTRT_BY_FORMAT(T, init_with, a, phi0, wall, ab, cq, dq, s);
 }
 
 template <typename T>
@@ -271,7 +273,7 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
     template hipError_t launch_sweep<T>(const SweepArgs<T>&, int, int, int, const LaunchCfg&, hipStream_t);       \
     template LaunchCfg resolve_launch<T>(const SweepArgs<T>&, int, int, int, LaunchCfg);                         \
     template hipError_t launch_init<T>(const SweepArgs<T>&, int, const double*, const double[4], const double[4],  \
-                                       const double[3], hipStream_t);                                              \
+                                       const double[3], const double[4], hipStream_t);                             \
     template hipError_t launch_gather_field<T>(const GatherArgs<T>&, int, hipStream_t);                           \
     template hipError_t launch_reduce<T>(const GatherArgs<T>&, int, int, double*, hipStream_t);                   \
     template hipError_t launch_convert<T>(const double*, T*, int, int, int, hipStream_t);                         \

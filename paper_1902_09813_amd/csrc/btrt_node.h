@@ -220,7 +220,13 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     const T kdx = fmadd(K11, dBx, K12 * dBy), kdy = fmadd(K12, dBx, K22 * dBy);
     const T jxp = fmadd(-half, kdx, (jx - kex) + dBx);
     const T jyp = fmadd(-half, kdy, (jy - key) + dBy);
-    const T phi3 = third * phi;
+    T phi3 = third * phi;
+    if (GEN && a.dpoly) {
+        // General model: D = d(phi) I; the equilibrium of pxx and pyy is d / 3 (Eq. (7), Eq. (9)),
+        // the other equilibrium moments do not depend on an isotropic D.
+        const T d = a.de != T(0) ? fmadd(a.dg, phi, a.de * abspow(phi, a.ds)) : a.dg * phi;
+        phi3 = third * d;
+    }
     const T s3 = third * s;
     const T pxxp = fmadd(-a.k2xx, pxx - phi3, pxx) + s3;
     const T pyyp = fmadd(-a.k2yy, pyy - phi3, pyy) + s3;
@@ -257,7 +263,8 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
 // f+(-1) at node (x, y) such that the first pull yields f(0) = f^eq(phi0) (Section 4): a value
 // whose consumer is an interior pull gets f^eq of Eq. (7) (D = phi I) at its destination; a
 // value whose consumer is the bounce-back rule gets 2 w phi_w - f^eq_opp at its own node.
-// ab = (ax, ay, bx, by), cq = (cx, cy, q): B(phi) = a phi + b phi^2 / 2 + c |phi|^q.
+// ab = (ax, ay, bx, by), cq = (cx, cy, q): B(phi) = a phi + b phi^2 / 2 + c |phi|^q; dq = (kind,
+// g, e, s): D(phi) = phi I (kind 0) or (g phi + e |phi|^s) I.
 // put(i, v) receives the value for direction i (FP64).
 __host__ __device__ inline void init_flux(double p, const double ab[4], const double cq[3], double& Bx, double& By)
 {
@@ -270,10 +277,24 @@ __host__ __device__ inline void init_flux(double p, const double ab[4], const do
     }
 }
 
+// w_i (phi + 3 c_i . B + 3/2 (d - phi)(|c_i|^2 - 2/3)) of Eq. (7) for D = d I.
+__host__ __device__ inline double init_feq(int i, double p, double Bx, double By, const double dq[4])
+{
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double wt[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    double v = p + 3.0 * (cx[i] * Bx + cy[i] * By);
+    if (dq[0] != 0.0) {
+        const double d = dq[1] * p + (dq[2] != 0.0 ? dq[2] * pow(fabs(p), dq[3]) : 0.0);
+        v += 1.5 * (d - p) * (cx[i] * cx[i] + cy[i] * cy[i] - 2.0 / 3.0);
+    }
+    return wt[i] * v;
+}
+
 template <typename Put>
 __host__ __device__ inline void init_values(const double* __restrict__ phi0, int x, int y, int nx, int ny, int perx,
                                             int pery, const double wall[4], const double ab[4], const double cq[3],
-                                            Put put)
+                                            const double dq[4], Put put)
 {
     constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -292,7 +313,7 @@ __host__ __device__ inline void init_values(const double* __restrict__ phi0, int
             const double p = phi0[static_cast<int64_t>(yd) * nx + xd];
             double Bx, By;
             init_flux(p, ab, cq, Bx, By);
-            v = wt[i] * (p + 3.0 * (cx[i] * Bx + cy[i] * By));
+            v = init_feq(i, p, Bx, By, dq);
         } else {
             // The link leaves through x- or x+ (y- or y+) according to the sign of c_i.
             const double vx = wall[cx[i] < 0 ? 0 : 1];
@@ -301,7 +322,7 @@ __host__ __device__ inline void init_values(const double* __restrict__ phi0, int
             const int o = opp[i];
             double Bx, By;
             init_flux(here, ab, cq, Bx, By);
-            const double feq_o = wt[o] * (here + 3.0 * (cx[o] * Bx + cy[o] * By));
+            const double feq_o = init_feq(o, here, Bx, By, dq);
             v = 2.0 * wt[i] * pw - feq_o;
         }
         put(i, v);

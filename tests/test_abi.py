@@ -144,3 +144,14 @@ def test_general_model_parameters_reach_the_library():
         _expect_inval(btrt.Problem(4, 4, precision=prec, flux_c=(0.1, 0.0), flux_q=2.0, **good))
     # Exponents are read only where their term is present.
     btrt.Problem(4, 4, flux_q=0.0, src_p=-1.0, **good).validate()
+
+
+def test_general_d_reaches_the_library():
+    good = dict(A0=(0.01, 0.0, 0.01))
+    btrt.Problem(4, 4, dterm=(1.0, 0.2, 3.0), **good).validate()
+    btrt.Problem(4, 4, precision=btrt.F32, dterm=(0.5, 0.0, 0.0), **good).validate()  # s unread when e = 0
+    assert "exponent s" in _expect_inval(btrt.Problem(4, 4, dterm=(1.0, 0.2, 0.5), **good))
+    _expect_inval(btrt.Problem(4, 4, dterm=(np.nan, 0.0, 1.0), **good))
+    _expect_inval(btrt.Problem(4, 4, dterm=(1.0, np.inf, 2.0), **good))
+    for prec in (btrt.F16DEV, btrt.BF16DEV):
+        assert "BTRT_F64 or BTRT_F32" in _expect_inval(btrt.Problem(4, 4, precision=prec, dterm=(1.0, 0.1, 2.0), **good))
