@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "btrt_oracle.c")
+SRCS = [os.path.join(HERE, "btrt_oracle.c"), os.path.join(HERE, "btrt3_oracle.c")]
 LIB = os.path.join(HERE, "liboracle_btrt.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
@@ -16,7 +16,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle; returns the path of the shared library."""
-    cmd = ["gcc", *CFLAGS, SRC, "-o", LIB + ".tmp", "-lm"]
+    cmd = ["gcc", *CFLAGS, *SRCS, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
