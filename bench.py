@@ -121,6 +121,35 @@ def timed_run(w, precision, steps, warmup, fusion=0, launch=None):
     }
 
 
+def timed_run3(w, precision, steps, warmup):
+    """The D3Q19 solver (one step per launch) on a Workload3: HIP events on the stream the library
+    launches on (a torch stream handed over through the grid), every launch timed together."""
+    import torch
+    from paper_1902_09813_amd import btrt3
+
+    prob = btrt3.problem_from_workload3(w, precision=precision, check_interval=CHECK_INTERVAL)
+    stream = torch.cuda.Stream()
+    prob.grid.stream = stream.cuda_stream
+    solver = btrt3.Solver3(prob, w.phi0())
+    info = solver.info()
+    solver.step(warmup)
+    solver.sync()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    solver.step(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    solver.close()
+    nodes = w.nx * w.ny * w.nz
+    bw = info.bytes_per_node_launch * nodes / (ms / steps * 1e-3) / 1e9
+    return {"mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "launch_us": round(ms / steps * 1e3, 2),
+            "bytes_per_node_launch": info.bytes_per_node_launch, "achieved_gbs": round(bw, 1),
+            "hbm_frac": round(bw / HBM_PEAK_GBS, 4), "steps": steps}
+
+
 def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=1200):
     """The 256 uneven FP32 instances: one batched launch per fused step (tuned) against a loop
     of plain per-instance launches on one stream. Returns MLUPS of both."""
@@ -300,6 +329,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served measurement")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--d3-only", action="store_true",
+                    help="only the D3Q19 side measurement (256^3 nonlinear periodic box), --steps steps")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -319,6 +350,13 @@ def main():
 
     from paper_1902_09813_amd import btrt
     from paper_1902_09813_amd import workloads as W
+
+    if args.d3_only:
+        w3 = W.d3_nonlinear(256, 256, 256)
+        p3 = btrt.F64 if args.precision == "f64" else btrt.F32
+        print(json.dumps({"workload": w3.name, "precision": args.precision,
+                          **timed_run3(w3, p3, args.steps, args.warmup)}), flush=True)
+        return
 
     precisions = {"f64": btrt.F64, "f32": btrt.F32, "f16dev": btrt.F16DEV, "bf16dev": btrt.BF16DEV}
     prec = precisions[args.precision]
@@ -364,6 +402,10 @@ def main():
         r3 = timed_run(w2, btrt.F64, 2000, 50, args.fusion)
         extra["c2_f64_mlups"] = round(r3["mlups"], 1)
         extra["c2_f64_launch_us"] = round(r3["launch_ms_avg"] * 1e3, 2)
+        w3 = W.d3_nonlinear(256, 256, 256)
+        for name, p3 in (("f64", btrt.F64), ("f32", btrt.F32)):
+            print(f"[bench] side measurement: {w3.name} (D3Q19) {name}", file=sys.stderr, flush=True)
+            extra[f"d3q19_256_{name}"] = timed_run3(w3, p3, 200, 20)
         print("[bench] side measurement: 256 batched instances vs per-instance loop (f32)", file=sys.stderr,
               flush=True)
         extra["batched_c4_f32"] = batched_vs_loop()

@@ -1,0 +1,64 @@
+// Internal interface between the host runtime of the D3Q19 solver (btrt3_api.cpp) and its
+// gfx950 kernels (btrt3_kernels.hip). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace btrt3k {
+
+constexpr int kQ = 19;
+
+// Everything one D3Q19 sweep needs, by value in the kernel argument segment.
+template <typename T>
+struct Sweep3 {
+    const T* fin;       // 19 planes of f+(t-1); plane stride `plane`
+    T* fout;            // 19 planes receiving f+(t)
+    const T* phi_prev;  // phi(t-1)
+    T* phi_out;         // phi(t)
+    const T* src;       // source plane (null: none)
+    int64_t plane;      // elements per plane: pitch * ny * nz
+    int nx, ny, nz, pitch;
+    int slab;           // pitch * ny
+    int per[3];         // 1 when the axis is periodic
+    T wall[6];          // phi_w of faces x-, x+, y-, y+, z-, z+
+    T a[3], b[3];       // B(phi) = a phi + b phi^2 / 2
+    T A0[6];            // (a11, a12, a13, a22, a23, a33) of A0, per-node K1 when beta > 0
+    T beta;
+    T K1[6];            // constant K1 (symmetric) in the same order
+    T k0;
+    T q2[6];            // K2 rates (k2_11, k2_12s, k2_13s, k2_22, k2_23s, k2_33), off-diagonals
+                        // symmetrised (Eq. (100))
+    int tiles_x, tiles_y;
+    int nts;            // 1: non-temporal stores
+};
+
+// Gather-reduce arguments: the sweep arguments of the current state plus the buffers.
+template <typename T>
+struct Gather3 {
+    Sweep3<T> s;
+    double* snap;       // residual: FP64 phi snapshot (dense), updated in place
+    const double* ref;  // error: reference (dense)
+    double* out;        // dense output of field and population reads
+    double* partial;    // per-block partial sums
+    int population;     // -1: phi
+};
+
+constexpr int kPartials = 6;
+constexpr int kReduceBlocks3 = 1024;
+
+template <typename T>
+hipError_t launch3_sweep(const Sweep3<T>& a, bool src, bool k1_per_node, hipStream_t s);
+// f+(-1) and phi(-1) := phi0 (FP64 values converted to T) into a.fout / a.phi_out.
+template <typename T>
+hipError_t launch3_init(const Sweep3<T>& a, const double* phi0, hipStream_t s);
+template <typename T>
+hipError_t launch3_gather(const Gather3<T>& a, hipStream_t s);
+// mode 0: residual (Eq. (64)); 1: error norms against ref (Eq. (63)); result: kPartials doubles.
+template <typename T>
+hipError_t launch3_reduce(const Gather3<T>& a, int mode, double* result, hipStream_t s);
+template <typename T>
+hipError_t launch3_convert(const double* in, T* out, int nx, int ny, int nz, int pitch, hipStream_t s);
+
+}  // namespace btrt3k

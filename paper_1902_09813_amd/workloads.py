@@ -40,6 +40,17 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           Eq. (62); phi0 and the Dirichlet values on all four walls from Eq. (68), the walls at
           time (k + 1) dt for the k-th step.
 
+* ``d3``   three-dimensional (D3Q19) problems: ``d3_hill(n)`` an n^3 periodic box, anisotropic
+          A0 = [[0.05, 0.01, 0.005], [0.01, 0.04, -0.008], [0.005, -0.008, 0.03]], B = phi u with
+          u = (0.02, -0.01, 0.015) 16/n (diffusive scaling), phi0 the 3-D Gaussian of sigma n/6 at the
+          box centre (periodic images |m| <= 1), k0 = k2 = 1; ``d3_nonlinear(nx, ny, nz)`` periodic,
+          B = 0.025 phi^2 (1, 1, 1) + phi (0.01, 0, -0.01), A(phi) = diag(0.01, 0.008, 0.006)(1 + phi^2),
+          phi0 a sum of 12 Gaussians (seed 7; amplitude U[0, 1], sigma U[0.06, 0.15] of the shortest side,
+          centres uniform, minimum image), k0 = k2 = 1 (the 3-D counterpart of c3);
+          ``d3_walls(nx, ny, nz)`` six Dirichlet faces phi_w = (0.2, 0.5, 0.3, 0.6, 0.4, 0.1),
+          A0 full, beta = 0.5, B = phi (0.02, 0.01, -0.015) + 0.01 phi^2 (1, 0, 0), S = 1e-3 sin sin sin
+          at cell centres, phi0 ~ U[0, 1) (seed 8), K2 rates 0.9 .. 1.3.
+
 ``scaled`` variants keep every parameter and shrink the grid (for parity at oracle-friendly
 sizes; ragged sizes exercise partial tiles).
 """
@@ -242,3 +253,90 @@ def c5(count: int, rate: float, seed: int = 5, side_range=(64, 2048), tol: float
         w.name = f"c5_{k:04d}_{w.nx}"
         out.append((t, w, tol, max_steps))
     return out
+
+
+@dataclass
+class Workload3:
+    """A D3Q19 problem in lattice units (faces x-, x+, y-, y+, z-, z+; A0 = (a11, a12, a13, a22, a23,
+    a33)); phi0 and the source are (nz, ny, nx) arrays."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    steps: int
+    flux_a: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    flux_b: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    A0: Tuple[float, ...] = (0.0,) * 6
+    beta: float = 0.0
+    source: Optional[np.ndarray] = None
+    bc_type: Tuple[int, ...] = (PERIODIC,) * 6
+    bc_value: Tuple[float, ...] = (0.0,) * 6
+    k0: float = 1.0
+    k2: object = 1.0
+    phi0_array: Optional[np.ndarray] = None
+    extra: dict = field(default_factory=dict)
+
+    def phi0(self) -> np.ndarray:
+        return self.phi0_array
+
+
+D3_A0 = np.array([[0.05, 0.01, 0.005], [0.01, 0.04, -0.008], [0.005, -0.008, 0.03]])
+
+
+def _centres3(nx, ny, nz):
+    return np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+
+
+def d3_hill(n: int = 24, steps: Optional[int] = None) -> Workload3:
+    """Periodic n^3 box, anisotropic A0, convection scaled with 16/n, the 3-D Gaussian of sigma n/6."""
+    A = D3_A0
+    u = np.array([0.02, -0.01, 0.015]) * 16 / n
+    s0 = n / 6
+    z, y, x = _centres3(n, n, n)
+    phi0 = np.zeros((n, n, n))
+    Si = np.eye(3) / s0 ** 2
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                d = np.stack([x - n / 2 - i * n, y - n / 2 - j * n, z - n / 2 - k * n])
+                phi0 += np.exp(-0.5 * np.einsum("a...,ab,b...->...", d, Si, d))
+    steps = int(round(40 * (n / 16) ** 2)) if steps is None else steps
+    return Workload3(f"d3_hill_{n}", n, n, n, steps, flux_a=tuple(u), A0=(A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2],
+                     A[2, 2]), phi0_array=phi0, extra={"sigma": s0, "u": u, "A": A})
+
+
+def d3_nonlinear(nx: int = 256, ny: int = 256, nz: int = 256, steps: int = 200, seed: int = 7) -> Workload3:
+    """Periodic box, Burgers-type flux plus linear convection, A(phi) = diag(0.01, 0.008, 0.006)(1 + phi^2),
+    phi0 a seeded sum of 12 Gaussians (minimum image)."""
+    rng = np.random.default_rng(seed)
+    m = min(nx, ny, nz)
+    amp = rng.uniform(0.0, 1.0, 12)
+    sig = rng.uniform(0.06, 0.15, 12) * m
+    cen = rng.uniform(0.0, 1.0, (12, 3)) * np.array([nx, ny, nz])
+    phi0 = np.zeros((nz, ny, nx))
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    z = np.arange(nz) + 0.5
+    for a, s, c in zip(amp, sig, cen):
+        dx = x - c[0]
+        dx -= nx * np.round(dx / nx)
+        dy = y - c[1]
+        dy -= ny * np.round(dy / ny)
+        dz = z - c[2]
+        dz -= nz * np.round(dz / nz)
+        gx, gy, gz = np.exp(-dx * dx / (2 * s * s)), np.exp(-dy * dy / (2 * s * s)), np.exp(-dz * dz / (2 * s * s))
+        phi0 += a * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+    return Workload3(f"d3_nonlinear_{nx}x{ny}x{nz}", nx, ny, nz, steps, flux_a=(0.01, 0.0, -0.01),
+                     flux_b=(0.025, 0.025, 0.025), A0=(0.01, 0.0, 0.0, 0.008, 0.0, 0.006), beta=1.0, phi0_array=phi0)
+
+
+def d3_walls(nx: int = 37, ny: int = 29, nz: int = 23, steps: int = 120, seed: int = 8) -> Workload3:
+    """Six Dirichlet faces, full anisotropic A0 with beta = 0.5, a sine source, random phi0."""
+    z, y, x = _centres3(nx, ny, nz)
+    S = 1e-3 * np.sin(np.pi * x / nx) * np.sin(np.pi * y / ny) * np.sin(np.pi * z / nz)
+    phi0 = np.random.default_rng(seed).random((nz, ny, nx))
+    A = D3_A0
+    return Workload3(f"d3_walls_{nx}x{ny}x{nz}", nx, ny, nz, steps, flux_a=(0.02, 0.01, -0.015),
+                     flux_b=(0.01, 0.0, 0.0), A0=(A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]), beta=0.5,
+                     source=S, bc_type=(DIRICHLET,) * 6, bc_value=(0.2, 0.5, 0.3, 0.6, 0.4, 0.1),
+                     k2=(0.9, 1.1, 1.0, 1.2, 1.3, 0.95, 1.05, 0.85, 1.15), phi0_array=phi0)

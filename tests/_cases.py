@@ -69,3 +69,25 @@ def run_oracle(w, steps=None, nthreads=0) -> "O.Oracle":
 def normwise(a, ref):
     """max |a - ref| / max |ref| (the normwise relative error used for parity)."""
     return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
+def oracle3_problem(w):
+    """The oracle's D3Q19 problem for a workloads.Workload3."""
+    from oracle import oracle3 as O3
+
+    if isinstance(w.k2, str):
+        assert w.k2 == "hbb"
+        k2 = (O.k2_hbb(O.k1_isotropic(w.A0[0])),) * 9
+    elif np.isscalar(w.k2):
+        k2 = (float(w.k2),) * 9
+    else:
+        k2 = tuple(w.k2)
+    return O3.Problem3(w.nx, w.ny, w.nz, flux_a=w.flux_a, flux_b=w.flux_b, A0=w.A0, beta=w.beta, k0=w.k0, K2=k2,
+                       bc_type=w.bc_type, bc_value=w.bc_value)
+
+
+def run_oracle3(w, steps=None, nthreads=0):
+    from oracle import oracle3 as O3
+
+    o = O3.Oracle3(oracle3_problem(w), w.phi0(), source=w.source, nthreads=nthreads)
+    return o.step(w.steps if steps is None else steps)
