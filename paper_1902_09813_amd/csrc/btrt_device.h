@@ -818,7 +818,7 @@ int walk_waves_per_cu()
 }
 
 // Automatic launch shape (measured on gfx950 over 256^2 .. 4096^2 grids):
-//  - steps: 4 per launch from 2^20 nodes up (the state no longer fits the caches and the
+//  - steps: kAutoFuse (4) per launch from 2^20 nodes up (the state no longer fits the caches and the
 //    strip walkers cut its traffic), one per launch below;
 //  - strip rows: the largest of 32, 16, 8 that still gives every resident wavefront slot about
 //    two strips (rows at least 8);
@@ -844,7 +844,7 @@ void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
 template <typename F, int SRC, int KP>
 LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
 {
-    if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kMaxFuse : 1;
+    if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kAutoFuse : 1;
     if (cfg.steps != 2) cfg.tile = 0;
     if (cfg.steps == 1) {  // rows: tile height of the one-step kernel
         if (cfg.rows <= 0) cfg.rows = kTileY;
@@ -858,7 +858,9 @@ LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
     switch (cfg.steps) {
         case 2: walk_shape<F, SRC, KP, 2>(a, cfg); break;
         case 3: walk_shape<F, SRC, KP, 3>(a, cfg); break;
-        default: walk_shape<F, SRC, KP, 4>(a, cfg); break;
+        case 4: walk_shape<F, SRC, KP, 4>(a, cfg); break;
+        case 5: walk_shape<F, SRC, KP, 5>(a, cfg); break;
+        default: walk_shape<F, SRC, KP, 6>(a, cfg); break;
     }
     return cfg;
 }
@@ -905,7 +907,9 @@ hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t 
     switch (cfg.steps) {
         case 2: return walk_launch<F, SRC, KP, 2>(a, cfg, s);
         case 3: return walk_launch<F, SRC, KP, 3>(a, cfg, s);
-        default: return walk_launch<F, SRC, KP, 4>(a, cfg, s);
+        case 4: return walk_launch<F, SRC, KP, 4>(a, cfg, s);
+        case 5: return walk_launch<F, SRC, KP, 5>(a, cfg, s);
+        default: return walk_launch<F, SRC, KP, 6>(a, cfg, s);
     }
 }
 
