@@ -1,4 +1,6 @@
-"""Full-length FP64 parity at the benchmark sizes, in the benchmark's launch configuration.
+"""Full-length FP64 parity at the benchmark sizes, in the automatic launch shape and in the shape the
+benchmark's tuner settles on (six steps per launch with 64-row strips for the 4096^2 workload, the
+two-step LDS tile for the 1024^2 one; every shape gives the same bits, tested at small sizes).
 
 The oracle's full runs (1024 x 1024 for 20000 steps, 4096 x 4096 for 5000 steps) take minutes to
 an hour on a CPU, so their results are stored: tests/golden/make_full_length.py (which calls
@@ -21,7 +23,7 @@ from paper_1902_09813_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = [("c2", W.c2), ("c3", W.c3)]
+CASES = [("c2", W.c2, None), ("c2", W.c2, (2, 0, 0, 1)), ("c3", W.c3, None), ("c3", W.c3, (6, 64, 1, 0))]
 
 
 def load(w):
@@ -30,14 +32,16 @@ def load(w):
         return json.load(fh)
 
 
-@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
-def test_full_length_against_stored_oracle(name, make):
+@pytest.mark.parametrize("name,make,launch", CASES, ids=[f"{c[0]}-{c[2] or 'auto'}" for c in CASES])
+def test_full_length_against_stored_oracle(name, make, launch):
     w = make()
     ref = load(w)
     assert (ref["nx"], ref["ny"], ref["steps"]) == (w.nx, w.ny, w.steps)
-    print(f"[gpu] full length {w.name}: {w.nx}x{w.ny} x {w.steps} steps", flush=True)
+    print(f"[gpu] full length {w.name}: {w.nx}x{w.ny} x {w.steps} steps, launch {launch or 'automatic'}", flush=True)
     sys.stdout.flush()
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0(), torch_memory=True) as s:
+        if launch:
+            s.set_launch(*launch)
         s.step(w.steps)
         phi = s.field()
         f = s.populations()
