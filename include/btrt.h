@@ -276,6 +276,31 @@ int btrt_sync(btrt_t* h);
 /* Derived constants plus the number of steps taken. */
 int btrt_get_info(const btrt_t* h, btrt_info_t* info);
 
+/* ---- checkpoint and resume -------------------------------------------------------------
+ * A checkpoint holds the solver state between steps: the step count, the stored populations
+ * f+(t-1) and phi(t-1) in the handle's storage format, the Eq. (64) residual snapshot, the
+ * Dirichlet values the next pull reads, and a copy of the problem's derived constants. It is
+ * plain host memory, laid out by the library (a header, then the arrays), valid on any handle
+ * of the same library build. Per-node inputs (a source field, an A0 field) are not stored: the
+ * handle a checkpoint is restored into must be created with the same problem. */
+
+/* Bytes a checkpoint of h takes. */
+int btrt_checkpoint_size(const btrt_t* h, size_t* bytes);
+
+/* Writes the state of h into buf (host memory owned by the caller, at least
+ * btrt_checkpoint_size bytes). Waits for the handle's stream. Errors: BTRT_E_INVAL for a NULL or
+ * short buffer; BTRT_E_DEVICE. */
+int btrt_checkpoint(btrt_t* h, void* buf, size_t bytes);
+
+/* Loads a checkpoint into h, which must have been created with the same problem: grid,
+ * precision and every derived constant (K1, K2, k0, flux, diffusion, source, walls, storage
+ * scale) must match, else BTRT_E_INVAL with nothing changed. The handle continues from the
+ * checkpoint's step with the bits the original handle would have produced (its own launch shape
+ * is kept; every shape gives the same bits). A checkpoint taken under a wall schedule restores
+ * the values in force; btrt_set_walls must then give the values of the following steps before
+ * the handle steps again. Synchronises. */
+int btrt_restore(btrt_t* h, const void* buf, size_t bytes);
+
 /* Frees the handle and the device memory the library allocated. Synchronises. */
 int btrt_destroy(btrt_t* h);
 

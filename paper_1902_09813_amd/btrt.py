@@ -29,6 +29,7 @@ EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "
            "btrt_set_fusion", "btrt_tune", "btrt_field",
            "btrt_populations", "btrt_residual", "btrt_error", "btrt_solve", "btrt_sync",
            "btrt_get_info", "btrt_destroy", "btrt_strerror", "btrt_last_error",
+           "btrt_checkpoint_size", "btrt_checkpoint", "btrt_restore",
            "btrt_batch_create", "btrt_batch_step", "btrt_batch_field", "btrt_batch_residual",
            "btrt_batch_set_config", "btrt_batch_get_config", "btrt_batch_tune", "btrt_batch_steps",
            "btrt_batch_sync", "btrt_batch_destroy",
@@ -171,6 +172,9 @@ def lib() -> ctypes.CDLL:
             "btrt_sync": ([hp], ctypes.c_int),
             "btrt_get_info": ([hp, P(Info)], ctypes.c_int),
             "btrt_destroy": ([hp], ctypes.c_int),
+            "btrt_checkpoint_size": ([hp, P(ctypes.c_size_t)], ctypes.c_int),
+            "btrt_checkpoint": ([hp, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+            "btrt_restore": ([hp, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
             "btrt_batch_create": ([ctypes.c_int32, P(ProblemDesc), ctypes.c_int32, ctypes.c_void_p, P(hp)], ctypes.c_int),
             "btrt_batch_step": ([hp, ctypes.c_int64], ctypes.c_int),
             "btrt_batch_field": ([hp, ctypes.c_int32, dp], ctypes.c_int),
@@ -381,6 +385,20 @@ class Solver:
         info = Info()
         _check(lib().btrt_get_info(self.h, ctypes.byref(info)), "btrt_get_info")
         return info
+
+    def checkpoint(self) -> bytes:
+        """btrt_checkpoint: the solver state as bytes."""
+        n = ctypes.c_size_t()
+        _check(lib().btrt_checkpoint_size(self.h, ctypes.byref(n)), "btrt_checkpoint_size")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().btrt_checkpoint(self.h, buf, n.value), "btrt_checkpoint")
+        return buf.raw
+
+    def restore(self, data: bytes) -> "Solver":
+        """btrt_restore: load a checkpoint taken from a handle of the same problem."""
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(lib().btrt_restore(self.h, buf, len(data)), "btrt_restore")
+        return self
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <string>
 #include <vector>
@@ -92,9 +93,192 @@ void release(btrt* h)
     delete h;
 }
 
+// ---- checkpoint layout ---------------------------------------------------------------------
+// [header (kCkHeader bytes)] [f: 9 planes, storage format] [phi: one plane] [snapshot: nx*ny FP64]
+// [wall entry: 2 (nx + ny) values in the phi type, general node model only]
+constexpr char kCkMagic[8] = {'B', 'T', 'R', 'T', 'C', 'K', 'P', '1'};
+constexpr int kCkParams = 48;
+constexpr size_t kCkHeader = 512;
+
+struct CkHeader {
+    char magic[8];
+    int32_t nx, ny, precision, pitch;
+    int64_t step;
+    int64_t f_bytes, phi_bytes, snap_bytes, wall_bytes;
+    int32_t wall_mode;  // 0: per-side constants or none; 1: a wall schedule was active
+    int32_t pad;
+    double params[kCkParams];
+};
+static_assert(sizeof(CkHeader) <= kCkHeader, "checkpoint header");
+
+template <typename T>
+void ck_params_of(const SweepArgs<T>& a, const Instance& I, double p[kCkParams])
+{
+    int k = 0;
+    auto put = [&](double v) { p[k++] = v; };
+    for (double v : I.info.K1) put(v);
+    for (double v : I.info.K2) put(v);
+    put(I.info.k0);
+    put(a.ax); put(a.ay); put(a.bx); put(a.by); put(a.fcx); put(a.fcy); put(a.fq);
+    put(a.a11); put(a.a12); put(a.a22); put(a.beta);
+    put(a.rr); put(a.rp); put(a.dg); put(a.de); put(a.ds); put(a.dpoly);
+    put(a.src_amp);
+    for (int q = 0; q < 4; ++q) put(a.wall[q]);
+    put(a.dev_scale);
+    put(I.kind); put(I.kmode() & btrtk::kK1Mask); put(I.perx); put(I.pery); put(I.growth);
+    while (k < kCkParams) put(0.0);
+}
+
+void ck_params(const Instance& I, double p[kCkParams])
+{
+    if (I.precision == BTRT_F64)
+        ck_params_of(I.a64, I, p);
+    else
+        ck_params_of(I.a32, I, p);
+}
+
+struct CkSizes {
+    size_t f, phi, snap, wall, total;
+};
+
+CkSizes ck_sizes(const Instance& I)
+{
+    CkSizes z{};
+    const size_t ps = I.precision == BTRT_F64 ? 8 : 4;
+    z.f = 9 * static_cast<size_t>(I.plane) * pop_bytes(I.precision);
+    z.phi = static_cast<size_t>(I.plane) * ps;
+    z.snap = static_cast<size_t>(I.nx) * I.ny * 8;
+    z.wall = I.gen ? static_cast<size_t>(I.wall_entry_values()) * ps : 0;
+    z.total = kCkHeader + z.f + z.phi + z.snap + z.wall;
+    return z;
+}
+
 }  // namespace
 
 extern "C" {
+
+int btrt_checkpoint_size(const btrt_t* h, size_t* bytes)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (!bytes) return fail(BTRT_E_INVAL, "bytes is NULL");
+    *bytes = ck_sizes(h->inst).total;
+    return ok();
+}
+
+int btrt_checkpoint(btrt_t* h, void* buf, size_t bytes)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    const Instance& I = h->inst;
+    const CkSizes z = ck_sizes(I);
+    if (!buf || bytes < z.total) return fail(BTRT_E_INVAL, "checkpoint buffer of %zu bytes < %zu", bytes, z.total);
+    DeviceGuard g(h->device);
+    if (g.status() != hipSuccess) return hip_fail(g.status(), "hipSetDevice");
+    CkHeader hd{};
+    std::memcpy(hd.magic, kCkMagic, sizeof(kCkMagic));
+    hd.nx = I.nx;
+    hd.ny = I.ny;
+    hd.precision = I.precision;
+    hd.pitch = I.pitch;
+    hd.step = I.step;
+    hd.f_bytes = static_cast<int64_t>(z.f);
+    hd.phi_bytes = static_cast<int64_t>(z.phi);
+    hd.snap_bytes = static_cast<int64_t>(z.snap);
+    hd.wall_bytes = static_cast<int64_t>(z.wall);
+    hd.wall_mode = I.wall_limit != INT64_MAX ? 1 : 0;
+    ck_params(I, hd.params);
+    char* out = static_cast<char*>(buf);
+    std::memset(out, 0, kCkHeader);
+    std::memcpy(out, &hd, sizeof(hd));
+    char* p = out + kCkHeader;
+    hipError_t e = hipMemcpyAsync(p, I.mem + I.L.f[I.cur], z.f, hipMemcpyDeviceToHost, h->stream);
+    p += z.f;
+    if (e == hipSuccess) e = hipMemcpyAsync(p, I.mem + I.L.phi[I.cur], z.phi, hipMemcpyDeviceToHost, h->stream);
+    p += z.phi;
+    if (e == hipSuccess) e = hipMemcpyAsync(p, I.mem + I.L.snap, z.snap, hipMemcpyDeviceToHost, h->stream);
+    p += z.snap;
+    if (e == hipSuccess && z.wall) {
+        const size_t es = I.precision == BTRT_F64 ? 8 : 4;
+        const char* cur = I.wtab + static_cast<size_t>(I.step - I.wall_t0) * I.wall_stride * es;
+        e = hipMemcpyAsync(p, cur, z.wall, hipMemcpyDeviceToHost, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "checkpoint copy");
+}
+
+int btrt_restore(btrt_t* h, const void* buf, size_t bytes)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    Instance& I = h->inst;
+    if (!buf || bytes < kCkHeader) return fail(BTRT_E_INVAL, "not a checkpoint (too short)");
+    CkHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kCkMagic, sizeof(kCkMagic)) != 0) return fail(BTRT_E_INVAL, "not a checkpoint");
+    const CkSizes z = ck_sizes(I);
+    if (hd.nx != I.nx || hd.ny != I.ny || hd.precision != I.precision || hd.pitch != I.pitch)
+        return fail(BTRT_E_INVAL, "checkpoint of a %d x %d grid (precision %d) restored into a %d x %d grid (%d)",
+                    hd.nx, hd.ny, hd.precision, I.nx, I.ny, I.precision);
+    const size_t ps = I.precision == BTRT_F64 ? 8 : 4;
+    const size_t wall_entry = static_cast<size_t>(I.wall_entry_values()) * ps;
+    const size_t wall = static_cast<size_t>(hd.wall_bytes);
+    if (hd.f_bytes != static_cast<int64_t>(z.f) || hd.phi_bytes != static_cast<int64_t>(z.phi) ||
+        hd.snap_bytes != static_cast<int64_t>(z.snap) || (wall != 0 && wall != wall_entry) ||
+        bytes < kCkHeader + z.f + z.phi + z.snap + wall || hd.step < 0 || (hd.wall_mode == 1 && wall == 0))
+        return fail(BTRT_E_INVAL, "checkpoint sizes do not match this handle");
+    double params[kCkParams];
+    ck_params(I, params);
+    for (int k = 0; k < kCkParams; ++k)
+        if (std::memcmp(&params[k], &hd.params[k], sizeof(double)) != 0)
+            return fail(BTRT_E_INVAL, "checkpoint of a different problem (derived constant %d differs)", k);
+    DeviceGuard g(h->device);
+    if (g.status() != hipSuccess) return hip_fail(g.status(), "hipSetDevice");
+    const char* p = static_cast<const char*>(buf) + kCkHeader;
+    // The general node model by the problem itself (a power-law flux, a phi-dependent source or
+    // D != phi I; the same on both sides, as the constants match) keeps its one-entry table in
+    // the workspace; a checkpoint taken under a wall schedule brings the values then in force,
+    // which become a one-entry table of their own (steps wait for btrt_set_walls).
+    const SweepArgs<double>& a64 = I.a64;
+    const SweepArgs<float>& a32 = I.a32;
+    const bool problem_gen = I.precision == BTRT_F64
+                                 ? (a64.fcx != 0 || a64.fcy != 0 || a64.rr != 0 || a64.dpoly)
+                                 : (a32.fcx != 0 || a32.fcy != 0 || a32.rr != 0 || a32.dpoly);
+    void* wmem = nullptr;
+    if (hd.wall_mode == 1) {
+        if (hipMalloc(&wmem, wall) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BTRT_E_NOMEM, "hipMalloc of %zu bytes for the wall values failed", wall);
+        }
+    } else if ((wall != 0) != problem_gen) {
+        return fail(BTRT_E_INVAL, "checkpoint of a different problem (node model differs)");
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(I.mem + I.L.f[I.cur], p, z.f, hipMemcpyHostToDevice, h->stream);
+    p += z.f;
+    if (e == hipSuccess) e = hipMemcpyAsync(I.mem + I.L.phi[I.cur], p, z.phi, hipMemcpyHostToDevice, h->stream);
+    p += z.phi;
+    if (e == hipSuccess) e = hipMemcpyAsync(I.mem + I.L.snap, p, z.snap, hipMemcpyHostToDevice, h->stream);
+    p += z.snap;
+    if (e == hipSuccess && wall) {
+        char* dst = wmem ? static_cast<char*>(wmem) : I.mem + I.L.wall0;
+        e = hipMemcpyAsync(dst, p, wall, hipMemcpyHostToDevice, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        if (wmem) (void)hipFree(wmem);
+        return hip_fail(e, "restore copy");
+    }
+    I.step = hd.step;
+    if (h->wsched) {
+        (void)hipFree(h->wsched);  // the stream is idle
+        h->wsched = nullptr;
+    }
+    I.gen = wall != 0;
+    I.wtab = wmem ? static_cast<const char*>(wmem) : (wall ? I.mem + I.L.wall0 : nullptr);
+    h->wsched = wmem;
+    I.wall_t0 = hd.step;
+    I.wall_stride = 0;
+    I.wall_limit = wmem ? hd.step : INT64_MAX;
+    return ok();
+}
 
 int btrt_validate(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
                   const btrt_source_t* R, const btrt_bc_t* bc, const btrt_relax_t* relax, btrt_info_t* info)
