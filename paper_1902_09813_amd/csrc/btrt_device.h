@@ -6,13 +6,14 @@
 //   1. pull  f_i(x, t) = f_i+(x - c_i, t-1)                         (Eq. (38))
 //      or, when x - c_i lies beyond a Dirichlet wall,
 //            f_i(x, t) = -f_opp(i)+(x, t-1) + 2 w_i phi_w             (Eqs. (54)-(56))
-//   2. moments m = T f (Eq. (88)), phi = m_0 (Eq. (9))
-//   3. block relaxation in moment space with S_f of Eq. (99), the equilibrium moments
-//      of Eq. (7) with D = phi I, the source of Eq. (8) and G of Eq. (11)
-//   4. f+ = T^-1 m+ and aligned stores of f+(t) and phi(t)
+//   2. phi, j and P (rows of Eq. (88)) from sums and differences of opposite populations
+//   3. Eq. (6): f_i+ = (1 - k0) f_i + w_i [E_i + 3 c_i . q], the moments the block relaxation
+//      of Eq. (99) changes (j with K1, P with K2) folded into q and E_i, with the equilibrium
+//      of Eq. (7), the source of Eq. (8) and G of Eq. (11)
+//   4. aligned stores of f+(t) and phi(t)
 // Reads and writes are disjoint (two population buffers), so no synchronisation is needed.
-// The 9x9 transform is a handful of adds per node and stays in registers: the sweep is
-// bound by HBM bandwidth, not by arithmetic, so there is no matrix-core work here.
+// A node update is about a hundred FP64 operations in registers, with no dense contraction:
+// there is no matrix-core work here.
 //
 // Storage formats: plain FP64 or FP32 planes, or 16-bit planes (FP16 or BF16) of scaled
 // deviations from equilibrium, h_i = q(s (f_i+ - f_i^eq(phi))), with phi(t) in FP32 at the
@@ -345,7 +346,7 @@ constexpr int kShl1 = 0x130;  // DPP wave_shl:1, lane j receives lane j+1
 template <int CTRL>
 __device__ __forceinline__ int lane_shift_b32(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
 
 template <int CTRL>
@@ -588,12 +589,13 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
         const WalkRow w = walk_row(q, a.ny, a.pery);
         Level<T>& cur = st.mid[PH][l - 2];
         T g[9];
-        T phi = T(0);
+        T phi;
         if (q >= L.ys - (K - l)) {
             phi = walk_collide<T, SRC, KM, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, l - 1, g);
         } else {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = T(0);
+            for (int i = 0; i < 9; ++i) g[i] = lev.f[i];
+            phi = lev.phi;
         }
         st.up[l - 2][0] = cur.f[2];
         st.up[l - 2][1] = cur.f[5];

@@ -1,6 +1,6 @@
 // Per-node pieces of the B-TriRT D2Q9 sweep (Zhao, Wu, Chai & Shi, arXiv:1902.09813):
-// the pull with half-way bounce-back (Eq. (38), Eqs. (54)-(56)) and the moment-space
-// collision (Eqs. (88), (99), (7), (8), (11)). Host-callable as well, so the same code can be
+// the pull with half-way bounce-back (Eq. (38), Eqs. (54)-(56)) and the collision of Eq. (6)
+// (with Eqs. (7), (8), (11), (30)). Host-callable as well, so the same code can be
 // exercised on the CPU; the library itself only runs it inside its kernels.
 #pragma once
 
@@ -150,16 +150,25 @@ __host__ __device__ inline T feq_dir(int i, T phi, T ax, T ay, T bx, T by)
     }
 }
 
+// phi = sum_i f_i (Eq. (9)), summed over pairs of opposite directions; collide forms the same
+// sums, so the phi a sweep writes and the phi a gather returns have the same bits.
 template <typename T>
 __host__ __device__ inline T sum9(const T f[9])
 {
-    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    return (f[0] + (f[1] + f[3])) + ((f[2] + f[4]) + ((f[5] + f[7]) + (f[6] + f[8])));
 }
 
-// One node of the B-TriRT collision in moment space; f holds f(x, t) on entry and
-// f+(x, t) on return. Returns phi(t). The library is built without floating-point
-// contraction: every fused multiply-add below is written out, so a node update rounds the
-// same way in every kernel that inlines it.
+// One node of the B-TriRT collision; f holds f(x, t) on entry and f+(x, t) on return. Returns
+// phi(t). Eq. (6) with f^neq = f - f^eq is used in the form
+//     f_i+ = (1 - k0) f_i + w_i [E_i + 3 c_i . q],
+//     q    = k0 j + dB - K1 (M1 + dB/2),                      (M1 = j - B, Eq. (10); G of Eq. (11))
+//     E_i  = k0 phi + s + 3/2 tr Q - 9/2 c_i^T Q c_i,        Q = (K2 - k0) o M2,
+// where M2 = P - (d/3) I is the second moment of f^neq (P = sum c c f, Eq. (9)) and, for
+// D = d I != phi I, Q gains -k0 (d - phi)/3 on the diagonal (the D term of f^eq in Eq. (7)), so
+// only phi, j and P are needed: the moments the block relaxation (Eq. (99)) changes; all others
+// relax with k0 through (1 - k0) f_i. The library is built without floating-point contraction:
+// every fused multiply-add below is written out, so a node update rounds the same way in every
+// kernel that inlines it.
 // KM (K1Mode, plus kGen) selects where K1 comes from and the node model; n is the node's
 // in-plane index (read only for an A0 field). s is the part of the source term of the step that
 // does not depend on phi, with the Scheme 2 correction folded in.
@@ -169,22 +178,18 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     constexpr int K1M = KM & kK1Mask;
     constexpr bool GEN = (KM & kGen) != 0;
     constexpr T third = T(1) / T(3);
-    constexpr T sixth = T(1) / T(6);
-    constexpr T twelfth = T(1) / T(12);
-    constexpr T ninth = T(1) / T(9);
-    constexpr T half = T(0.5), quarter = T(0.25);
+    constexpr T half = T(0.5);
 
-    // Moments m = T f, rows of Eq. (88).
-    const T phi = sum9(f);
-    const T jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
-    const T jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
-    const T sd = (f[5] + f[6]) + (f[7] + f[8]);
-    const T pxx = (f[1] + f[3]) + sd;
-    const T pyy = (f[2] + f[4]) + sd;
-    const T pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const T m6 = fmadd(-third, jy, (f[5] + f[6]) - (f[7] + f[8]));
-    const T m7 = fmadd(-third, jx, (f[5] + f[8]) - (f[6] + f[7]));
-    const T m8 = fmadd(-third, pxx + pyy, sd);
+    // phi, j and P (rows of Eq. (88)) from sums and differences of opposite populations.
+    const T s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
+    const T d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const T sd = s57 + s68;
+    const T phi = sum9(f);  // (f0 + s13) + (s24 + sd)
+    const T jx = d13 + (d57 - d68);
+    const T jy = d24 + (d57 + d68);
+    const T pxx = s13 + sd;
+    const T pyy = s24 + sd;
+    const T pxy = s57 - s68;
 
     // Flux B(phi) = phi (a + b phi / 2) and its backward difference over one step (the
     // correction G of Eq. (11)).
@@ -233,51 +238,49 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
         K22 = m11 * rdet;
     }
 
-    // Block relaxation (Eq. (99)) towards the equilibrium moments of Eq. (7) with D = phi I:
-    // (phi, B, phi/3, 0, phi/3, 0, 0, -phi/9); the source s (Eq. (8)) enters as s (1, 0, 0,
-    // 1/3, 0, 1/3, 0, 0, -1/9); G adds (I - K1/2) dB to j.
-    const T ex = jx - Bx, ey = jy - By;
-    const T kex = fmadd(K11, ex, K12 * ey), key = fmadd(K12, ex, K22 * ey);
-    const T kdx = fmadd(K11, dBx, K12 * dBy), kdy = fmadd(K12, dBx, K22 * dBy);
-    const T jxp = fmadd(-half, kdx, (jx - kex) + dBx);
-    const T jyp = fmadd(-half, kdy, (jy - key) + dBy);
-    T phi3 = third * phi;
-    if (GEN && a.dpoly) {
-        // General model: D = d(phi) I; the equilibrium of pxx and pyy is d / 3 (Eq. (7), Eq. (9)),
-        // the other equilibrium moments do not depend on an isotropic D.
-        const T d = a.de != T(0) ? fmadd(a.dg, phi, a.de * abspow(phi, a.ds)) : a.dg * phi;
-        phi3 = third * d;
-    }
-    const T s3 = third * s;
-    const T pxxp = fmadd(-a.k2xx, pxx - phi3, pxx) + s3;
-    const T pyyp = fmadd(-a.k2yy, pyy - phi3, pyy) + s3;
-    const T pxyp = (T(1) - a.k2xy) * pxy;
-    const T om0 = T(1) - a.k0;
-    const T m6p = om0 * m6;
-    const T m7p = om0 * m7;
-    const T m8p = fmadd(-ninth, s, fmadd(-a.k0, fmadd(ninth, phi, m8), m8));
-    const T phip = phi + s;
+    // Odd part: q = k0 j + dB - K1 (j - B + dB/2).
+    const T k0 = a.k0;
+    const T hx = fmadd(half, dBx, jx - Bx), hy = fmadd(half, dBy, jy - By);
+    const T qx = fmadd(k0, jx, dBx) - fmadd(K11, hx, K12 * hy);
+    const T qy = fmadd(k0, jy, dBy) - fmadd(K12, hx, K22 * hy);
 
-    // f+ = T^-1 m+ (dual basis of the rows of T).
-    const T pp = pxxp + pyyp;
-    f[0] = fmadd(T(-2) * third, pp, phip) + m8p;
-    const T c13 = fmadd(third, pxxp, fmadd(-sixth, pyyp, -half * m8p));
-    const T d13 = fmadd(third, jxp, -half * m7p);
-    f[1] = c13 + d13;
-    f[3] = c13 - d13;
-    const T c24 = fmadd(third, pyyp, fmadd(-sixth, pxxp, -half * m8p));
-    const T d24 = fmadd(third, jyp, -half * m6p);
-    f[2] = c24 + d24;
-    f[4] = c24 - d24;
-    const T e = fmadd(twelfth, pp, quarter * m8p);
-    const T h57 = fmadd(quarter, pxyp, e);
-    const T g57 = fmadd(twelfth, jxp + jyp, quarter * (m6p + m7p));
-    f[5] = h57 + g57;
-    f[7] = h57 - g57;
-    const T h68 = fmadd(-quarter, pxyp, e);
-    const T g68 = fmadd(twelfth, jyp - jxp, quarter * (m6p - m7p));
-    f[6] = h68 + g68;
-    f[8] = h68 - g68;
+    // Even part: Q = (K2 - k0) o (P - d/3 I) with d = phi (D = phi I) or the general model's d.
+    T d3 = third * phi;
+    T diag = T(0);
+    if (GEN && a.dpoly) {
+        // General model: D = d(phi) I; the equilibrium of P is d/3 I (Eq. (9)) and f^eq of
+        // Eq. (7) gains 3/2 (d - phi)(|c|^2 - 2/3) w_i, i.e. -k0 (d - phi)/3 on Q's diagonal.
+        const T d = a.de != T(0) ? fmadd(a.dg, phi, a.de * abspow(phi, a.ds)) : a.dg * phi;
+        d3 = third * d;
+        diag = (-k0 * third) * (d - phi);
+    }
+    T Qxx = (a.k2xx - k0) * (pxx - d3);
+    T Qyy = (a.k2yy - k0) * (pyy - d3);
+    const T Qxy = (a.k2xy - k0) * pxy;
+    if (GEN && a.dpoly) {
+        Qxx = Qxx + diag;
+        Qyy = Qyy + diag;
+    }
+    const T trQ = Qxx + Qyy;
+    const T base = fmadd(T(1.5), trQ, fmadd(k0, phi, s));
+
+    // f+ per direction pair: (1 - k0) f_i + w_i E_i +- 3 w_i c_i . q.
+    const T om0 = T(1) - k0;
+    constexpr T w0 = Lat<T>::w0, w1 = Lat<T>::w1, w5 = Lat<T>::w5;
+    f[0] = fmadd(om0, f[0], w0 * base);
+    const T ex = w1 * fmadd(T(-4.5), Qxx, base), ox = (T(3) * w1) * qx;
+    f[1] = fmadd(om0, f[1], ex + ox);
+    f[3] = fmadd(om0, f[3], ex - ox);
+    const T ey = w1 * fmadd(T(-4.5), Qyy, base), oy = (T(3) * w1) * qy;
+    f[2] = fmadd(om0, f[2], ey + oy);
+    f[4] = fmadd(om0, f[4], ey - oy);
+    const T ed = fmadd(T(-4.5), trQ, base);
+    const T e57 = w5 * fmadd(T(-9), Qxy, ed), o57 = (T(3) * w5) * (qx + qy);
+    f[5] = fmadd(om0, f[5], e57 + o57);
+    f[7] = fmadd(om0, f[7], e57 - o57);
+    const T e68 = w5 * fmadd(T(9), Qxy, ed), o68 = (T(3) * w5) * (qy - qx);
+    f[6] = fmadd(om0, f[6], e68 + o68);
+    f[8] = fmadd(om0, f[8], e68 - o68);
     return phi;
 }
 
