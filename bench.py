@@ -72,7 +72,7 @@ def timed_run(w, precision, steps, warmup, fusion=0, launch=None):
     elif fusion:
         solver.set_fusion(fusion)
     else:
-        _, tuned = solver.tune(700)
+        _, tuned = solver.tune(900)
     shape = solver.launch()
     fusion = shape[0]
     solver.step(max(0, warmup - tuned))
@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", choices=["f64", "f32", "f16dev", "bf16dev"], default="f64")
-    ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4, 5, 6], default=0,
+    ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4, 5, 6, 7], default=0,
                     help="time steps per sweep launch (0: tuned during the warm-up)")
     ap.add_argument("--launch", default="",
                     help="fixed launch shape steps,rows,group,tile for the main measurement (default: tuned)")
@@ -390,7 +390,7 @@ def main():
             extra[f"c3_{name}_mlups"] = round(r2["mlups"], 1)
             extra[f"c3_{name}_hbm_frac"] = round(
                 r2["bytes_per_node_launch"] * r2["nodes"] / (r2["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        for k in (1, 2, 3, 4, 5, 6):
+        for k in (1, 2, 3, 4, 5, 6, 7):
             print(f"[bench] side measurement: {w.name} {args.precision}, {k} steps per launch", file=sys.stderr,
                   flush=True)
             rk = timed_run(w, prec, min(args.steps, 1000), 20, k)

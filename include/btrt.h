@@ -213,7 +213,7 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps);
 
 /* Shape of the sweep launches btrt_step makes. Every shape gives bitwise identical results;
  * only the speed differs. Zero fields are chosen by the library for the grid.
- *   steps_per_launch  1 .. 6 time steps per launch (0: 4 from 2^20 nodes up, else 1). With
+ *   steps_per_launch  1 .. 7 time steps per launch (0: 4 from 2^20 nodes up, else 1). With
  *                     k >= 2 each wavefront walks a strip of 66 - 2k columns down the grid and
  *                     keeps the k - 1 intermediate time levels in registers, so the state is
  *                     read and written once per k steps. Step counts that are not a multiple of
@@ -230,7 +230,7 @@ typedef struct {
     int32_t tile;
 } btrt_launch_t;
 
-/* Sets the launch shape; fields as above. Errors: BTRT_E_INVAL (steps outside [0, 6],
+/* Sets the launch shape; fields as above. Errors: BTRT_E_INVAL (steps outside [0, 7],
  * strip_rows < 0 or, with one step per launch, not 0, 1, 2, 4, 8 or 16, strips_per_group not
  * 0, 1 or 4, tile without steps_per_launch 2). */
 int btrt_set_launch(btrt_t* h, const btrt_launch_t* cfg);
@@ -238,12 +238,12 @@ int btrt_set_launch(btrt_t* h, const btrt_launch_t* cfg);
 /* The launch shape in force, with the automatic fields resolved for this grid. */
 int btrt_get_launch(btrt_t* h, btrt_launch_t* cfg);
 
-/* Shorthand for btrt_set_launch({steps_per_launch, 0, 0, 0}); steps_per_launch in [1, 6]
+/* Shorthand for btrt_set_launch({steps_per_launch, 0, 0, 0}); steps_per_launch in [1, 7]
  * (BTRT_E_INVAL otherwise). */
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch);
 
 /* Times candidate launch shapes on the handle's own state and keeps the fastest (per step):
- * one step per launch (tiles of 4, 8, 16 rows), the LDS tile, and strip walkers over 2 .. 6 steps x 8, 16, 32, 64, 128 rows
+ * one step per launch (tiles of 4, 8, 16 rows), the LDS tile, and strip walkers over 2 .. 7 steps x 8, 16, 32, 64, 128 rows
  * x 1, 4 strips per group, each for one untimed and two timed launches, as far as max_steps
  * allows. The state advances by *steps_used steps (the same bits btrt_step would give);
  * the Eq. (64) snapshot is not touched. Synchronises. best (may be NULL) receives the shape

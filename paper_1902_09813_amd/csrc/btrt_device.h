@@ -862,7 +862,8 @@ LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
         case 3: walk_shape<F, SRC, KP, 3>(a, cfg); break;
         case 4: walk_shape<F, SRC, KP, 4>(a, cfg); break;
         case 5: walk_shape<F, SRC, KP, 5>(a, cfg); break;
-        default: walk_shape<F, SRC, KP, 6>(a, cfg); break;
+        case 6: walk_shape<F, SRC, KP, 6>(a, cfg); break;
+        default: walk_shape<F, SRC, KP, 7>(a, cfg); break;
     }
     return cfg;
 }
@@ -911,7 +912,8 @@ hipError_t sweep_variant(SweepArgs<typename F::T> a, LaunchCfg cfg, hipStream_t 
         case 3: return walk_launch<F, SRC, KP, 3>(a, cfg, s);
         case 4: return walk_launch<F, SRC, KP, 4>(a, cfg, s);
         case 5: return walk_launch<F, SRC, KP, 5>(a, cfg, s);
-        default: return walk_launch<F, SRC, KP, 6>(a, cfg, s);
+        case 6: return walk_launch<F, SRC, KP, 6>(a, cfg, s);
+        default: return walk_launch<F, SRC, KP, 7>(a, cfg, s);
     }
 }
 

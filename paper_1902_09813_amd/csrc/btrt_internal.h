@@ -24,7 +24,7 @@ enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
 constexpr int kK1Mask = 3;
 constexpr int kGen = 4;
 
-constexpr int kMaxFuse = 6;   // most time steps one sweep launch can fuse
+constexpr int kMaxFuse = 7;   // most time steps one sweep launch can fuse
 constexpr int kAutoFuse = 4;  // steps per launch of the automatic shape on large grids
 
 // Everything one sweep needs, by value in the kernel argument segment.

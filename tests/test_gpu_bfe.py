@@ -78,7 +78,7 @@ def test_fp64_parity_with_oracle(w):
 
 
 SHAPES = [(1, 4, 0, 0), (1, 16, 0, 0), (2, 0, 0, 1), (2, 8, 1, 0), (3, 16, 4, 0), (4, 8, 1, 0), (4, 32, 4, 0),
-          (4, 128, 1, 0), (5, 16, 4, 0), (6, 32, 1, 0)]
+          (4, 128, 1, 0), (5, 16, 4, 0), (6, 32, 1, 0), (7, 64, 1, 0)]
 
 
 @pytest.mark.parametrize("precision", [btrt.F64, btrt.F32], ids=["f64", "f32"])

@@ -18,7 +18,7 @@ from tests.test_gpu_parity import custom
 pytestmark = pytest.mark.gpu
 
 # The tuner's candidate shapes: (steps_per_launch, strip_rows, strips_per_group, tile).
-SHAPES = [(1, 0, 0, 0), (1, 1, 0, 0), (1, 8, 0, 0), (1, 16, 0, 0), (2, 0, 0, 1)] + [(k, r, g, 0) for k in (2, 3, 4, 5, 6) for r in (8, 16, 32, 64, 128) for g in (1, 4)]
+SHAPES = [(1, 0, 0, 0), (1, 1, 0, 0), (1, 8, 0, 0), (1, 16, 0, 0), (2, 0, 0, 1)] + [(k, r, g, 0) for k in (2, 3, 4, 5, 6, 7) for r in (8, 16, 32, 64, 128) for g in (1, 4)]
 
 GRIDS = [
     custom("walls_mixed", 150, 83, 0, bc_type=(1, 1, 0, 0), bc_value=(0.3, 0.8, 0, 0), flux_b=(0.04, -0.03),
@@ -56,7 +56,7 @@ def test_tune_advances_the_state_like_plain_steps(w):
         assert s.info().step == used
         assert s.launch() == shape
         k, rows, group, tile = shape
-        assert 1 <= k <= 6 and group in (0, 1, 4) and tile in (0, 1)
+        assert 1 <= k <= 7 and group in (0, 1, 4) and tile in (0, 1)
         s.step(13)
         got = s.populations()
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as r:
@@ -84,7 +84,7 @@ def test_automatic_shape_by_grid_size():
 def test_invalid_launch_shapes_are_rejected():
     w = W.c1(1.0)
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
-        for bad in [(7, 0, 0, 0), (-1, 0, 0, 0), (2, -1, 0, 0), (2, 16, 3, 0), (3, 0, 0, 1), (1, 0, 0, 1),
+        for bad in [(8, 0, 0, 0), (-1, 0, 0, 0), (2, -1, 0, 0), (2, 16, 3, 0), (3, 0, 0, 1), (1, 0, 0, 1),
                     (1, 3, 0, 0), (1, 32, 0, 0)]:
             with pytest.raises(btrt.BtrtError) as e:
                 s.set_launch(*bad)

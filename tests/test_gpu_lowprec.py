@@ -37,7 +37,7 @@ def solver(w, precision):
     return btrt.Solver(btrt.problem_from_workload(w, precision=precision), w.phi0())
 
 
-@pytest.mark.parametrize("k", [2, 4, 6])
+@pytest.mark.parametrize("k", [2, 4, 6, 7])
 @pytest.mark.parametrize("precision", FORMATS, ids=lambda p: FMT_ID[p])
 @pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
 def test_fused_launch_is_bitwise_identical(w, precision, k):

@@ -139,7 +139,7 @@ def test_torch_memory_and_stream_bitwise_identical(w):
     assert np.array_equal(pa, pb)
 
 
-@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("w", CASES, ids=lambda w: w.name)
 def test_fused_launch_is_bitwise_identical(w, k):
     # k steps per launch (strip walkers, intermediate levels in registers) must give the bits
@@ -161,7 +161,7 @@ WALK_SHAPES = [(57, 17), (58, 16), (59, 33), (60, 31), (62, 47), (116, 15), (125
 WALK_BCS = [(0, 0, 0, 0), (1, 1, 1, 1), (0, 0, 1, 1), (1, 1, 0, 0)]
 
 
-@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("shape", WALK_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
 def test_walker_strip_edges_bitwise(shape, k):
     nx, ny = shape
@@ -180,7 +180,7 @@ def test_walker_strip_edges_bitwise(shape, k):
 def test_fusion_outside_range_is_rejected():
     w = W.c1(1.0)
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
-        for k in (0, 7, -1):
+        for k in (0, 8, -1):
             with pytest.raises(btrt.BtrtError) as e:
                 s.set_fusion(k)
             assert e.value.code == btrt.E_INVAL
