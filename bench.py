@@ -121,9 +121,10 @@ def timed_run(w, precision, steps, warmup, fusion=0, launch=None):
     }
 
 
-def timed_run3(w, precision, steps, warmup):
-    """The D3Q19 solver (one step per launch) on a Workload3: HIP events on the stream the library
-    launches on (a torch stream handed over through the grid), every launch timed together."""
+def timed_run3(w, precision, steps, warmup, launch=None):
+    """The D3Q19 solver on a Workload3: HIP events on the stream the library launches on (a torch
+    stream handed over through the grid), every launch timed together. launch: a fixed
+    (steps_per_launch, z_chunk, tile), else the library's automatic shape."""
     import torch
     from paper_1902_09813_amd import btrt3
 
@@ -131,6 +132,9 @@ def timed_run3(w, precision, steps, warmup):
     stream = torch.cuda.Stream()
     prob.grid.stream = stream.cuda_stream
     solver = btrt3.Solver3(prob, w.phi0())
+    if launch:
+        solver.set_launch(*launch)
+    shape = solver.launch()
     info = solver.info()
     solver.step(warmup)
     solver.sync()
@@ -144,8 +148,12 @@ def timed_run3(w, precision, steps, warmup):
     ms = a.elapsed_time(b)
     solver.close()
     nodes = w.nx * w.ny * w.nz
-    bw = info.bytes_per_node_launch * nodes / (ms / steps * 1e-3) / 1e9
-    return {"mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "launch_us": round(ms / steps * 1e3, 2),
+    k = shape[0]
+    launches = steps // k + steps % k
+    launch_ms = ms / launches
+    bw = info.bytes_per_node_launch * nodes / (launch_ms * 1e-3) / 1e9
+    return {"mlups": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "launch_us": round(launch_ms * 1e3, 2),
+            "launch": {"steps_per_launch": shape[0], "z_chunk": shape[1], "tile": shape[2]},
             "bytes_per_node_launch": info.bytes_per_node_launch, "achieved_gbs": round(bw, 1),
             "hbm_frac": round(bw / HBM_PEAK_GBS, 4), "steps": steps}
 
@@ -329,6 +337,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served measurement")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--d3-launch", default="",
+                    help="with --d3-only: fixed D3Q19 launch shape steps,z_chunk,tile (default: automatic)")
     ap.add_argument("--d3-only", action="store_true",
                     help="only the D3Q19 side measurement (256^3 nonlinear periodic box), --steps steps")
     args = ap.parse_args()
@@ -352,10 +362,11 @@ def main():
     from paper_1902_09813_amd import workloads as W
 
     if args.d3_only:
+        launch3 = tuple(int(v) for v in args.d3_launch.split(",")) if args.d3_launch else None
         w3 = W.d3_nonlinear(256, 256, 256)
         p3 = btrt.F64 if args.precision == "f64" else btrt.F32
         print(json.dumps({"workload": w3.name, "precision": args.precision,
-                          **timed_run3(w3, p3, args.steps, args.warmup)}), flush=True)
+                          **timed_run3(w3, p3, args.steps, args.warmup, launch3)}), flush=True)
         return
 
     precisions = {"f64": btrt.F64, "f32": btrt.F32, "f16dev": btrt.F16DEV, "bf16dev": btrt.BF16DEV}

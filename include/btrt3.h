@@ -103,8 +103,32 @@ int btrt3_validate(const btrt3_grid_t* grid, const btrt3_flux_t* B, const btrt3_
 int btrt3_create(const btrt3_grid_t* grid, const btrt3_flux_t* B, const btrt3_diff_t* K, const btrt3_source_t* R,
                  const btrt3_bc_t* bc, const btrt3_relax_t* relax, const double* phi0, btrt3_t** out);
 
-/* Enqueues n >= 0 time steps (one launch each) and returns without waiting. */
+/* Enqueues n >= 0 time steps and returns without waiting: one launch per step, or with two
+ * steps per launch (btrt3_set_launch) n/2 launches of two steps and, for odd n, one of one. */
 int btrt3_step(btrt3_t* h, int64_t n);
+
+/* Launch shape of btrt3_step. Every shape gives bitwise identical results; only the speed differs.
+ *   steps_per_launch  1 or 2 (0: automatic, 2 from 2^21 nodes up, else 1). With 2, a workgroup
+ *                     owns an xy tile of columns plus a one-column halo ring and walks z over a
+ *                     chunk of planes: step 1 of each plane goes to LDS, step 2 of the plane below
+ *                     is computed from it, so the state is read and written once per two steps.
+ *   z_chunk           two-step launches: output planes per workgroup (0: automatic, about eight
+ *                     workgroups per compute unit over the launch, at least 16 planes)
+ *   tile              two-step launches, threads per workgroup (output columns): 1 = 64 x 8
+ *                     (62 x 6), 2 = 32 x 16 (30 x 14), 3 = 32 x 8 (30 x 6), 4 = 16 x 16 (14 x 14);
+ *                     0: automatic (1) */
+typedef struct {
+    int32_t steps_per_launch;
+    int32_t z_chunk;
+    int32_t tile;
+} btrt3_launch_t;
+
+/* Sets the launch shape; fields as above. Errors: BTRT_E_INVAL (steps_per_launch outside
+ * [0, 2], z_chunk < 0, tile outside [0, 4]); BTRT_E_STATE for a NULL handle. */
+int btrt3_set_launch(btrt3_t* h, const btrt3_launch_t* cfg);
+
+/* The launch shape in force, with the automatic fields resolved for this grid. */
+int btrt3_get_launch(const btrt3_t* h, btrt3_launch_t* cfg);
 
 /* phi(t) (nx*ny*nz values) into host memory; synchronises. */
 int btrt3_field(btrt3_t* h, double* phi_out);

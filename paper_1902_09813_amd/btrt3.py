@@ -11,8 +11,9 @@ from paper_1902_09813_amd.btrt import (BtrtError, F32, F64, K2_HBB, K2_VALUE, SR
                                         lib as _lib2)
 
 # Every function include/btrt3.h declares.
-EXPORTS = ("btrt3_validate", "btrt3_create", "btrt3_step", "btrt3_field", "btrt3_populations", "btrt3_residual",
-           "btrt3_error", "btrt3_solve", "btrt3_sync", "btrt3_get_info", "btrt3_destroy")
+EXPORTS = ("btrt3_validate", "btrt3_create", "btrt3_step", "btrt3_set_launch", "btrt3_get_launch", "btrt3_field",
+           "btrt3_populations", "btrt3_residual", "btrt3_error", "btrt3_solve", "btrt3_sync", "btrt3_get_info",
+           "btrt3_destroy")
 
 __all__ = ["Problem3", "Solver3", "problem_from_workload3", "BtrtError", "F64", "F32", "EXPORTS"]
 
@@ -43,6 +44,13 @@ class Relax3(ctypes.Structure):
                 ("check_interval", ctypes.c_int32)]
 
 
+class Launch3(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int32), ("z_chunk", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.steps_per_launch, self.z_chunk, self.tile)
+
+
 class Info3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("pitch", ctypes.c_int32), ("k1_per_node", ctypes.c_int32),
@@ -65,6 +73,8 @@ def lib() -> ctypes.CDLL:
             "btrt3_validate": ([P(Grid3), P(Flux3), P(Diff3), P(Source3), P(BC3), P(Relax3), P(Info3)], ctypes.c_int),
             "btrt3_create": ([P(Grid3), P(Flux3), P(Diff3), P(Source3), P(BC3), P(Relax3), dp, P(hp)], ctypes.c_int),
             "btrt3_step": ([hp, ctypes.c_int64], ctypes.c_int),
+            "btrt3_set_launch": ([hp, P(Launch3)], ctypes.c_int),
+            "btrt3_get_launch": ([hp, P(Launch3)], ctypes.c_int),
             "btrt3_field": ([hp, dp], ctypes.c_int),
             "btrt3_populations": ([hp, dp], ctypes.c_int),
             "btrt3_residual": ([hp, dp], ctypes.c_int),
@@ -134,6 +144,17 @@ class Solver3:
     def step(self, n: int) -> "Solver3":
         _check(lib().btrt3_step(self.h, int(n)), "btrt3_step")
         return self
+
+    def set_launch(self, steps_per_launch: int, z_chunk: int = 0, tile: int = 0) -> "Solver3":
+        cfg = Launch3(int(steps_per_launch), int(z_chunk), int(tile))
+        _check(lib().btrt3_set_launch(self.h, ctypes.byref(cfg)), "btrt3_set_launch")
+        return self
+
+    def launch(self):
+        """(steps_per_launch, z_chunk, tile) in force, automatic fields resolved."""
+        cfg = Launch3()
+        _check(lib().btrt3_get_launch(self.h, ctypes.byref(cfg)), "btrt3_get_launch")
+        return cfg.as_tuple()
 
     def field(self) -> np.ndarray:
         out = np.empty(self.problem.shape)

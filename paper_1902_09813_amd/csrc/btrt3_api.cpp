@@ -177,6 +177,8 @@ struct btrt3 {
     int cur = 0;
     int64_t step = 0;
     int check_interval = 1000;
+    int cus = 256;                          // compute units of the device
+    btrt3_launch_t launch{0, 0, 0};         // as set (0: automatic)
     Sweep3<double> a64{};
     Sweep3<float> a32{};
     btrt3_info_t info{};
@@ -284,6 +286,23 @@ int setup(btrt3* h, const btrt3_flux_t* B, const btrt3_diff_t* K, const btrt3_so
     return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "init");
 }
 
+// Launch shape with the automatic fields resolved for the handle's grid.
+btrt3_launch_t resolve_launch(const btrt3* h)
+{
+    btrt3_launch_t c = h->launch;
+    const int64_t nodes = static_cast<int64_t>(h->nx) * h->ny * h->nz;
+    if (c.steps_per_launch == 0) c.steps_per_launch = nodes >= (int64_t(1) << 21) ? 2 : 1;
+    if (c.tile == 0) c.tile = 1;
+    if (c.z_chunk == 0) {
+        // About eight workgroups per compute unit over a launch, chunks of at least 16 planes.
+        const int64_t xy = sweep2_workgroups(h->nx, h->ny, 1, c.tile, 1);
+        const int64_t target = 8LL * h->cus;
+        const int64_t planes = std::max<int64_t>((h->nz * xy + target - 1) / target, 16);
+        c.z_chunk = static_cast<int>(std::min<int64_t>(planes, h->nz));
+    }
+    return c;
+}
+
 int reduce_sync(btrt3* h, int mode, double out[kPartials])
 {
     double* result = reinterpret_cast<double*>(h->mem + h->L.result);
@@ -361,6 +380,9 @@ int btrt3_create(const btrt3_grid_t* grid, const btrt3_flux_t* B, const btrt3_di
         if (g.status() != hipSuccess) {
             rc = hip_fail(g.status(), "hipSetDevice");
         } else {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+                h->cus = cus;
             if (grid->stream) {
                 h->stream = static_cast<hipStream_t>(grid->stream);
             } else if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -392,14 +414,46 @@ int btrt3_step(btrt3_t* h, int64_t n)
     if (n < 0) return fail(BTRT_E_INVAL, "n = %lld < 0", static_cast<long long>(n));
     DeviceGuard g(h->device);
     if (g.status() != hipSuccess) return hip_fail(g.status(), "hipSetDevice");
-    for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = h->precision == BTRT_F64
-                           ? launch3_sweep<double>(args<double>(h, h->cur), h->src, h->k1_per_node, h->stream)
-                           : launch3_sweep<float>(args<float>(h, h->cur), h->src, h->k1_per_node, h->stream);
+    const btrt3_launch_t c = resolve_launch(h);
+    for (int64_t s = 0; s < n;) {
+        const bool two = c.steps_per_launch == 2 && n - s >= 2;
+        const bool f64 = h->precision == BTRT_F64;
+        hipError_t e;
+        if (two)
+            e = f64 ? launch3_sweep2<double>(args<double>(h, h->cur), h->src, h->k1_per_node, c.tile, c.z_chunk,
+                                             h->stream)
+                    : launch3_sweep2<float>(args<float>(h, h->cur), h->src, h->k1_per_node, c.tile, c.z_chunk,
+                                            h->stream);
+        else
+            e = f64 ? launch3_sweep<double>(args<double>(h, h->cur), h->src, h->k1_per_node, h->stream)
+                    : launch3_sweep<float>(args<float>(h, h->cur), h->src, h->k1_per_node, h->stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
         h->cur ^= 1;
-        ++h->step;
+        const int k = two ? 2 : 1;
+        s += k;
+        h->step += k;
     }
+    return ok();
+}
+
+int btrt3_set_launch(btrt3_t* h, const btrt3_launch_t* cfg)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (!cfg) return fail(BTRT_E_INVAL, "cfg is NULL");
+    if (cfg->steps_per_launch < 0 || cfg->steps_per_launch > 2)
+        return fail(BTRT_E_INVAL, "steps_per_launch = %d: must be 0, 1 or 2", cfg->steps_per_launch);
+    if (cfg->z_chunk < 0) return fail(BTRT_E_INVAL, "z_chunk = %d < 0", cfg->z_chunk);
+    if (cfg->tile < 0 || cfg->tile >= kTiles2)
+        return fail(BTRT_E_INVAL, "tile = %d: must be in [0, %d]", cfg->tile, kTiles2 - 1);
+    h->launch = *cfg;
+    return ok();
+}
+
+int btrt3_get_launch(const btrt3_t* h, btrt3_launch_t* cfg)
+{
+    if (!h) return fail(BTRT_E_STATE, "NULL handle");
+    if (!cfg) return fail(BTRT_E_INVAL, "cfg is NULL");
+    *cfg = resolve_launch(h);
     return ok();
 }
 

@@ -32,6 +32,7 @@ struct Sweep3 {
                         // symmetrised (Eq. (100))
     int tiles_x, tiles_y;
     int nts;            // 1: non-temporal stores
+    int zc;             // two-step kernel: output planes per workgroup
 };
 
 // Gather-reduce arguments: the sweep arguments of the current state plus the buffers.
@@ -50,6 +51,14 @@ constexpr int kReduceBlocks3 = 1024;
 
 template <typename T>
 hipError_t launch3_sweep(const Sweep3<T>& a, bool src, bool k1_per_node, hipStream_t s);
+// Two time steps in one launch (f+(t-1), phi(t-1) -> f+(t+1), phi(t+1)); the same bits as two
+// launch3_sweep calls. tile 1: 64 x 8 threads per workgroup, 2: 32 x 16, 3: 32 x 8, 4: 16 x 16;
+// zc output planes per workgroup (>= 1).
+constexpr int kTiles2 = 5;  // tile values 0 (automatic) .. 4
+template <typename T>
+hipError_t launch3_sweep2(const Sweep3<T>& a, bool src, bool k1_per_node, int tile, int zc, hipStream_t s);
+// Workgroups of a two-step launch for the grid (tile shape and z chunk as above).
+int64_t sweep2_workgroups(int nx, int ny, int nz, int tile, int zc);
 // f+(-1) and phi(-1) := phi0 (FP64 values converted to T) into a.fout / a.phi_out.
 template <typename T>
 hipError_t launch3_init(const Sweep3<T>& a, const double* phi0, hipStream_t s);

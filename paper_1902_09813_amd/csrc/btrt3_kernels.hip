@@ -240,6 +240,267 @@ __global__ __launch_bounds__(kBlock) void sweep3_kernel(Sweep3<T> a)
     store(a.phi_out + n, phi, a.nts);
 }
 
+// ---- two time steps per launch --------------------------------------------------------------
+// A workgroup of TXH x TYH threads owns an xy tile of (TXH - 2) x (TYH - 2) columns and walks z
+// over a chunk of zc output planes. Each thread holds one column of the tile plus its one-column
+// halo ring. Iteration it updates plane uz = z0 - 1 + it at step 1 (level 1: pull from f+(t-1)
+// in global memory, collide) and, from it = 2 on, plane uz - 1 at step 2 (level 2) on the
+// interior columns, pulling the level-1 populations of planes uz - 2 .. uz: those with c_xy != 0
+// from the neighbouring columns through LDS, those along z (0, 5, 6) and the bounce-back partners
+// from the thread's own registers. Level-1 values a neighbour pulls are published in LDS per
+// group of c_z: c_z = -1 (read in the same iteration, one slot), c_z = 0 (read one iteration
+// later, two slots), c_z = +1 (read two iterations later, three slots). Two barriers per
+// iteration (after publishing, after the level-2 reads). Both levels run pull3/collide3's
+// arithmetic, so a launch gives the bits of two one-step launches.
+//
+// Halo columns outside a Dirichlet face and planes outside the box along a Dirichlet z axis are
+// not nodes: they compute nothing, and no node reads them (it bounces back instead).
+
+// LDS slot of each direction's level-1 value (-1: kept in registers).
+__host__ __device__ constexpr int lds_pos(int i)
+{
+    //                        0   1  2  3  4   5   6  7  8  9 10 11 12 13 14 15 16 17 18
+    constexpr int v[19] = {-1, 0, 1, 2, 3, -1, -1, 4, 5, 6, 7, 0, 1, 0, 1, 2, 3, 2, 3};
+    return v[i];
+}
+constexpr int kSlotsD = 4;       // c_z = -1: directions 13, 14, 17, 18
+constexpr int kSlotsM = 2 * 8;   // c_z = 0: 1, 2, 3, 4, 7, 8, 9, 10, two planes
+constexpr int kSlotsU = 3 * 4;   // c_z = +1: 11, 12, 15, 16, three planes
+constexpr int kSlots = kSlotsD + kSlotsM + kSlotsU;
+
+template <int TXH, int TYH>
+struct Tile3x2 {
+    static constexpr int TX = TXH - 2, TY = TYH - 2, N = TXH * TYH;
+};
+
+// v mod n in [0, n) (a halo column of a ragged tile can lie more than one period away on a
+// grid narrower than the tile).
+__device__ __forceinline__ int wrap3(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Slot of direction i's level-1 value written in iteration `it` (a reader passes the iteration
+// that wrote it: plane pz - c_z was level 1's plane in iteration it - 1 - c_z).
+__device__ __forceinline__ int lds_slot(int i, int it)
+{
+    const int cz = czv(i);
+    if (cz < 0) return lds_pos(i);
+    if (cz == 0) return kSlotsD + 8 * (it & 1) + lds_pos(i);
+    return kSlotsD + kSlotsM + 4 * (it % 3) + lds_pos(i);
+}
+
+// Level-1 inputs of one column and plane as raw loads, issued an iteration before they are used:
+// each direction's value comes from x - c_i (wrapped on periodic axes) or, where that lies beyond
+// a Dirichlet face, from the node's own opposite population (resolved by raw3_resolve).
+template <typename T>
+struct Raw3 {
+    T v[kQ];
+    T phi;  // phi(t-1) of the node
+    T s;    // source
+};
+
+template <typename T, bool SRC, bool WALLS>
+__device__ __forceinline__ void raw3_issue(const Sweep3<T>& a, bool node, int x, int y, int z, Raw3<T>& r)
+{
+    if (!node) {  // not a node: nothing to load (the values are never read)
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) r.v[i] = T(0);
+        r.phi = r.s = T(0);
+        return;
+    }
+    const int64_t p = a.plane;
+    const int n = z * a.slab + y * a.pitch + x;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        int xs = x - cxv(i), ys = y - cyv(i), zs = z - czv(i);
+        bool out = false;
+        if (WALLS) {
+            if (xs < 0 || xs >= a.nx) { if (a.per[0]) xs = xs < 0 ? xs + a.nx : xs - a.nx; else out = true; }
+            if (ys < 0 || ys >= a.ny) { if (a.per[1]) ys = ys < 0 ? ys + a.ny : ys - a.ny; else out = true; }
+            if (zs < 0 || zs >= a.nz) { if (a.per[2]) zs = zs < 0 ? zs + a.nz : zs - a.nz; else out = true; }
+        } else {
+            xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+            ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
+            zs = zs < 0 ? zs + a.nz : (zs >= a.nz ? zs - a.nz : zs);
+        }
+        r.v[i] = out ? a.fin[oppv(i) * p + n] : a.fin[i * p + zs * a.slab + ys * a.pitch + xs];
+    }
+    r.phi = a.phi_prev[n];
+    r.s = SRC ? a.src[n] : T(0);
+}
+
+// f_i(x, t) from the raw loads: the bounce-back rule where x - c_i lies beyond Dirichlet faces
+// (one face: its phi_w; two: their mean), the arithmetic of pull3.
+template <typename T, bool WALLS>
+__device__ __forceinline__ void raw3_resolve(const Sweep3<T>& a, int x, int y, int z, const Raw3<T>& r, T f[kQ])
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        f[i] = r.v[i];
+        if constexpr (WALLS) {
+            const int xs = x - cxv(i), ys = y - cyv(i), zs = z - czv(i);
+            int faces = 0;
+            T wsum = T(0);
+            if (!a.per[0]) {
+                if (xs < 0) { ++faces; wsum += a.wall[0]; }
+                else if (xs >= a.nx) { ++faces; wsum += a.wall[1]; }
+            }
+            if (!a.per[1]) {
+                if (ys < 0) { ++faces; wsum += a.wall[2]; }
+                else if (ys >= a.ny) { ++faces; wsum += a.wall[3]; }
+            }
+            if (!a.per[2]) {
+                if (zs < 0) { ++faces; wsum += a.wall[4]; }
+                else if (zs >= a.nz) { ++faces; wsum += a.wall[5]; }
+            }
+            if (faces > 0) {
+                const T phiw = faces == 1 ? wsum : T(0.5) * wsum;
+                f[i] = fmadd(T(2) * wv<T>(i), phiw, -r.v[i]);
+            }
+        }
+    }
+}
+
+// Registers a column keeps of its own level-1 values for the next iteration: the directions no
+// LDS slot holds any more by then (0, 5, 6 and the c_z = -1 group), for i = 0, for the pull of
+// direction 5 one plane later and for bounce-back partners; -1: read back from LDS.
+__host__ __device__ constexpr int keep_pos(int i)
+{
+    //                        0   1   2   3   4  5  6   7   8   9  10  11  12 13 14  15  16 17 18
+    constexpr int v[19] = {0, -1, -1, -1, -1, 1, 2, -1, -1, -1, -1, -1, -1, 3, 4, -1, -1, 5, 6};
+    return v[i];
+}
+constexpr int kKeep = 7;
+
+template <typename T, bool SRC, bool KPHI, bool WALLS, int TXH, int TYH>
+__global__ __launch_bounds__(TXH* TYH) void sweep3x2_kernel(Sweep3<T> a)
+{
+    using G = Tile3x2<TXH, TYH>;
+    __shared__ T lds[kSlots][TYH][TXH];
+
+    const int t = xcd_tile();
+    const int per_chunk = a.tiles_x * a.tiles_y;
+    const int chunk = t / per_chunk;
+    const int rr = t - chunk * per_chunk;
+    const int tyi = rr / a.tiles_x, txi = rr - tyi * a.tiles_x;
+    const int lx = static_cast<int>(threadIdx.x % TXH), ly = static_cast<int>(threadIdx.x / TXH);
+
+    // This thread's column: unwrapped (ux, uy) and the grid node (x, y) it stands for.
+    const int ux = txi * G::TX - 1 + lx, uy = tyi * G::TY - 1 + ly;
+    bool col = true;
+    int x = ux, y = uy;
+    if (!WALLS || a.per[0]) x = wrap3(ux, a.nx); else col = col && ux >= 0 && ux < a.nx;
+    if (!WALLS || a.per[1]) y = wrap3(uy, a.ny); else col = col && uy >= 0 && uy < a.ny;
+    // Level 2 runs on interior columns that are nodes of the grid (not wrapped copies).
+    const bool interior = lx >= 1 && lx <= TXH - 2 && ly >= 1 && ly <= TYH - 2 && ux >= 0 && ux < a.nx && uy >= 0 &&
+                          uy < a.ny;
+    const int z0 = chunk * a.zc;
+    const int z1 = min(z0 + a.zc, a.nz);
+
+    T keep[kKeep];  // own level-1 values (keep_pos) of plane uz - 1
+    T prev_phi = T(0);
+    T f5pp = T(0);  // own level-1 f_5+ of plane uz - 2
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) keep[k] = T(0);
+
+    // Plane uz of the walk: wrapped plane index and whether (x, y, uz) is a node.
+    auto plane_of = [&](int uz, int& zz) {
+        zz = uz;
+        if (!WALLS || a.per[2]) {
+            zz = wrap3(uz, a.nz);
+            return col;
+        }
+        return col && uz >= 0 && uz < a.nz;
+    };
+    Raw3<T> raw;  // level-1 inputs of the next plane, loaded an iteration ahead
+    {
+        int zz;
+        const bool nd = plane_of(z0 - 1, zz);
+        raw3_issue<T, SRC, WALLS>(a, nd, x, y, zz, raw);
+    }
+
+    for (int it = 0; it <= z1 - z0 + 1; ++it) {
+        const int uz = z0 - 1 + it;
+        // Level 1 at (x, y, uz) from the loads issued an iteration ago.
+        T f[kQ];
+        T phi1 = T(0);
+        int zz;
+        const bool node1 = plane_of(uz, zz);
+        if (node1) {
+            raw3_resolve<T, WALLS>(a, x, y, zz, raw, f);
+            phi1 = collide3<T, KPHI>(a, f, raw.phi, raw.s);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) f[i] = T(0);
+        }
+        if (it <= z1 - z0) {  // the loads of the next plane, in flight during level 2
+            int zn;
+            const bool nd = plane_of(uz + 1, zn);
+            raw3_issue<T, SRC, WALLS>(a, nd, x, y, zn, raw);
+        }
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            if (lds_pos(i) >= 0) lds[lds_slot(i, it)][ly][lx] = f[i];
+        __syncthreads();
+
+        // Level 2 at plane pz = uz - 1 (an output plane of the chunk from it = 2 on).
+        if (it >= 2 && interior) {
+            const int pz = uz - 1;
+            const int pzz = (!WALLS || a.per[2]) ? wrap3(pz, a.nz) : pz;
+            T g[kQ];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const int cx = cxv(i), cy = cyv(i), cz = czv(i);
+                int faces = 0;
+                T wsum = T(0);
+                if constexpr (WALLS) {
+                    if (!a.per[0]) {
+                        if (ux - cx < 0) { ++faces; wsum += a.wall[0]; }
+                        else if (ux - cx >= a.nx) { ++faces; wsum += a.wall[1]; }
+                    }
+                    if (!a.per[1]) {
+                        if (uy - cy < 0) { ++faces; wsum += a.wall[2]; }
+                        else if (uy - cy >= a.ny) { ++faces; wsum += a.wall[3]; }
+                    }
+                    if (!a.per[2]) {
+                        if (pz - cz < 0) { ++faces; wsum += a.wall[4]; }
+                        else if (pz - cz >= a.nz) { ++faces; wsum += a.wall[5]; }
+                    }
+                }
+                if (faces > 0) {
+                    // Half-way bounce-back against the node's own level-1 value of the opposite
+                    // direction at plane pz (written to LDS in iteration it - 1, or kept).
+                    const int o = oppv(i);
+                    const T own = keep_pos(o) >= 0 ? keep[keep_pos(o)] : lds[lds_slot(o, it - 1)][ly][lx];
+                    const T phiw = faces == 1 ? wsum : T(0.5) * wsum;
+                    g[i] = fmadd(T(2) * wv<T>(i), phiw, -own);
+                } else if (i == 0) {
+                    g[i] = keep[0];
+                } else if (i == 5) {
+                    g[i] = f5pp;
+                } else if (i == 6) {
+                    g[i] = f[6];
+                } else {
+                    g[i] = lds[lds_slot(i, it - 1 - cz)][ly - cy][lx - cx];
+                }
+            }
+            const int n = pzz * a.slab + y * a.pitch + x;
+            const T phi2 = collide3<T, KPHI>(a, g, prev_phi, SRC ? a.src[n] : T(0));
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) store(a.fout + i * a.plane + n, g[i], a.nts);
+            store(a.phi_out + n, phi2, a.nts);
+        }
+        __syncthreads();
+        f5pp = keep[keep_pos(5)];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            if (keep_pos(i) >= 0) keep[keep_pos(i)] = f[i];
+        prev_phi = phi1;
+    }
+}
+
 // f+(-1): a value pulled by an interior neighbour is f^eq (Eq. (7), D = phi I) of that neighbour;
 // a value the bounce-back consumes at its own node is 2 w phi_w - f^eq of the opposite direction,
 // so the first pull yields f(0) = f^eq(phi0). FP64 arithmetic.
@@ -437,6 +698,60 @@ hipError_t launch3_sweep(const Sweep3<T>& in, bool src, bool k1_per_node, hipStr
     return hipGetLastError();
 }
 
+int64_t sweep2_workgroups(int nx, int ny, int nz, int tile, int zc)
+{
+    if (tile < 1 || tile >= kTiles2 || zc < 1) return 0;
+    constexpr int txs[5] = {0, 62, 30, 30, 14}, tys[5] = {0, 6, 14, 6, 14};
+    const int tx = txs[tile], ty = tys[tile];
+    return static_cast<int64_t>((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + zc - 1) / zc);
+}
+
+template <typename T, bool WALLS, int TXH, int TYH>
+hipError_t launch3_sweep2_shape(Sweep3<T> a, bool src, bool k1_per_node, int zc, hipStream_t s)
+{
+    using G = Tile3x2<TXH, TYH>;
+    a.tiles_x = (a.nx + G::TX - 1) / G::TX;
+    a.tiles_y = (a.ny + G::TY - 1) / G::TY;
+    a.zc = zc;
+    const int64_t wg = static_cast<int64_t>(a.tiles_x) * a.tiles_y * ((a.nz + zc - 1) / zc);
+    if (zc < 1 || wg > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(wg)), block(G::N);
+    if (src) {
+        if (k1_per_node)
+            hipLaunchKernelGGL((sweep3x2_kernel<T, true, true, WALLS, TXH, TYH>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep3x2_kernel<T, true, false, WALLS, TXH, TYH>), grid, block, 0, s, a);
+    } else {
+        if (k1_per_node)
+            hipLaunchKernelGGL((sweep3x2_kernel<T, false, true, WALLS, TXH, TYH>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep3x2_kernel<T, false, false, WALLS, TXH, TYH>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_sweep2(const Sweep3<T>& a, bool src, bool k1_per_node, int tile, int zc, hipStream_t s)
+{
+    const bool walls = !(a.per[0] && a.per[1] && a.per[2]);
+    switch (tile) {
+        case 1:
+            return walls ? launch3_sweep2_shape<T, true, 64, 8>(a, src, k1_per_node, zc, s)
+                         : launch3_sweep2_shape<T, false, 64, 8>(a, src, k1_per_node, zc, s);
+        case 2:
+            return walls ? launch3_sweep2_shape<T, true, 32, 16>(a, src, k1_per_node, zc, s)
+                         : launch3_sweep2_shape<T, false, 32, 16>(a, src, k1_per_node, zc, s);
+        case 3:
+            return walls ? launch3_sweep2_shape<T, true, 32, 8>(a, src, k1_per_node, zc, s)
+                         : launch3_sweep2_shape<T, false, 32, 8>(a, src, k1_per_node, zc, s);
+        case 4:
+            return walls ? launch3_sweep2_shape<T, true, 16, 16>(a, src, k1_per_node, zc, s)
+                         : launch3_sweep2_shape<T, false, 16, 16>(a, src, k1_per_node, zc, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch3_init(const Sweep3<T>& a, const double* phi0, hipStream_t s)
 {
@@ -483,6 +798,7 @@ hipError_t launch3_convert(const double* in, T* out, int nx, int ny, int nz, int
 
 #define BTRT3_INSTANTIATE(T)                                                                        \
     template hipError_t launch3_sweep<T>(const Sweep3<T>&, bool, bool, hipStream_t);                \
+    template hipError_t launch3_sweep2<T>(const Sweep3<T>&, bool, bool, int, int, hipStream_t);     \
     template hipError_t launch3_init<T>(const Sweep3<T>&, const double*, hipStream_t);              \
     template hipError_t launch3_gather<T>(const Gather3<T>&, hipStream_t);                          \
     template hipError_t launch3_reduce<T>(const Gather3<T>&, int, double*, hipStream_t);            \
