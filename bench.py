@@ -267,25 +267,44 @@ def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 
     }
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle as it stands, on the host cores, for a bounded number of steps."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s=12.0, budget_1thread_s=4.0):
+    """The FP64 oracle as it stands, on the host cores, for a bounded number of steps: all cores
+    (OpenMP over rows), then one thread."""
     from oracle import oracle as O
     from tests._cases import oracle_problem, oracle_source
 
-    o = O.Oracle(oracle_problem(w), w.phi0(), source=oracle_source(w))
-    t = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t
-    n = max(1, min(200, int(budget_s / max(one, 1e-6))))
-    t = time.perf_counter()
-    o.step(n)
-    el = time.perf_counter() - t
+    def timed(nthreads, budget):
+        o = O.Oracle(oracle_problem(w), w.phi0(), source=oracle_source(w), nthreads=nthreads)
+        t = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t
+        n = max(1, min(200, int(budget / max(one, 1e-6))))
+        t = time.perf_counter()
+        o.step(n)
+        return n, time.perf_counter() - t
+
+    n, el = timed(0, budget_s)
+    n1, el1 = timed(1, budget_1thread_s)
     return {
         "value": round(w.nx * w.ny * n / el / 1e6, 3),
         "unit": "MLUPS",
         "cores": O.threads(),
         "kind": "oracle",
         "sample": f"{w.name}: {n} steps of the {w.nx}x{w.ny} grid after 1 warm-up step ({el:.1f} s)",
+        "value_1thread": round(w.nx * w.ny * n1 / el1 / 1e6, 3),
+        "sample_1thread": f"{n1} steps after 1 warm-up step, one thread ({el1:.1f} s)",
+        "host_cpu": _cpu_model(),
     }
 
 
