@@ -333,9 +333,9 @@ typedef struct {
 } btrt_problem_t;
 
 /* How a batch launches: time steps fused per launch (1: 64 x 4 tiles; 2: the two-step LDS
- * tiles; 4: strip walkers, one wavefront per strip of 58 columns by strip_rows rows), resident
- * blocks per compute unit of the persistent grid (0: one block per tile or strip; with 4 steps
- * four one-wavefront blocks per unit), launches captured per HIP graph replay (0: no graph;
+ * tiles; 4, 6 or 7 = k: strip walkers, one wavefront per strip of 66 - 2k columns by strip_rows
+ * rows), resident blocks per compute unit of the persistent grid (0: one block per tile or
+ * strip; with a walker four one-wavefront blocks per unit), launches captured per HIP graph replay (0: no graph;
  * otherwise even, >= 2), and the walkers' strip height (0: 16; at most 4096). Every
  * configuration gives the same bits. */
 typedef struct {
@@ -372,10 +372,12 @@ int btrt_batch_get_config(const btrt_batch_t* b, btrt_batch_config_t* cfg);
 
 /* Autotuner: times each candidate configuration on the batch itself by running steps of the
  * solve (every configuration computes the same bits, so these steps count as ordinary
- * steps), at most max_steps in total; keeps and reports the fastest. Candidates: 4 steps per
- * launch with 16- and 32-row strips, 2 and 1 steps, each with 0 or 4 blocks per CU and with
- * or without 16-launch graphs, 4 warm-up and a multiple of 64 timed steps each (none when
- * max_steps < 16 * 68). *steps_used = steps taken. Synchronises. */
+ * steps), at most max_steps in total; keeps and reports the fastest per step. Candidates
+ * (10): walkers of 4, 6 and 7 steps with 16- and 32-row strips and 16-launch graphs; 4-step
+ * walkers with 32-row strips without graphs and with 4 blocks per CU; 2 steps with and without
+ * graphs; 1 step with graphs. Each takes k warm-up steps (k steps per launch) and a multiple of
+ * 16 k timed steps within max_steps / 10 (a candidate whose 17 k steps do not fit is skipped).
+ * *steps_used = steps taken. Synchronises. */
 int btrt_batch_tune(btrt_batch_t* b, int64_t max_steps, btrt_batch_config_t* best, int64_t* steps_used);
 
 /* Steps taken so far. */

@@ -10,11 +10,18 @@ hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const 
                               int flip, int steps, int grid, int rows, hipStream_t s)
 {
     if (total_tiles <= 0 || ninst <= 0) return hipSuccess;
-    if (steps == kBatchWalkK) {
+    if (batch_walks(steps)) {
         // Several resident strips per CU: a persistent grid of `grid` blocks covers the list.
         const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid * kWalkGroup, total_tiles) : total_tiles);
-        hipLaunchKernelGGL((batchw_kernel<T>), dim3(g), dim3(kWave), 0, s, ent, begin, par, ninst, total_tiles, flip,
-                           rows);
+        if (steps == 4)
+            hipLaunchKernelGGL((batchw_kernel<T, 4>), dim3(g), dim3(kWave), 0, s, ent, begin, par, ninst, total_tiles,
+                               flip, rows);
+        else if (steps == 6)
+            hipLaunchKernelGGL((batchw_kernel<T, 6>), dim3(g), dim3(kWave), 0, s, ent, begin, par, ninst, total_tiles,
+                               flip, rows);
+        else
+            hipLaunchKernelGGL((batchw_kernel<T, 7>), dim3(g), dim3(kWave), 0, s, ent, begin, par, ninst, total_tiles,
+                               flip, rows);
         return hipGetLastError();
     }
     const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid, total_tiles) : total_tiles);
@@ -25,7 +32,10 @@ hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const 
     return hipGetLastError();
 }
 
-int batch_strip_columns() { return Walk<kBatchWalkK>::W; }
+int batch_strip_columns(int steps)
+{
+    return steps == 4 ? Walk<4>::W : (steps == 6 ? Walk<6>::W : Walk<7>::W);
+}
 
 int tile_rows(int steps, int precision_bytes)
 {

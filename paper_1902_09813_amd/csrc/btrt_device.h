@@ -755,15 +755,12 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
 
 // Four steps per launch for a batch: the strips of every instance (58 columns by `rows` rows)
 // form the list; one wavefront per strip, no lockstep groups (instances differ in length).
-constexpr int kBatchWalkK = 4;
-
-template <typename T>
+template <typename T, int K>
 __global__ __launch_bounds__(kWave) void batchw_kernel(const BatchEntry<T>* __restrict__ ent,
                                                        const int* __restrict__ begin, const int* __restrict__ par,
                                                        int ninst, int total, int flip, int rows)
 {
     using F = Plain<T>;
-    constexpr int K = kBatchWalkK;
     const int g = static_cast<int>(gridDim.x);
     const int lane = static_cast<int>(threadIdx.x);
     for (int t = xcd_tile(); t < total; t += g) {

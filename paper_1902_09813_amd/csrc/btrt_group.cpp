@@ -47,12 +47,12 @@ hipError_t raw_launch(Group& g, int steps, int flip)
 }
 
 // Offsets of each member's units in the concatenated list for `steps` per launch: 64 x rows
-// tiles (1 and 2 steps), or strips of the 4-step walker (batch_strip_columns() x rows).
+// tiles (1 and 2 steps), or walker strips (batch_strip_columns(steps) x rows).
 int upload_begin(Group& g, int steps, int rows)
 {
     const int n = static_cast<int>(g.inst.size());
     std::vector<int> begin(n + 1);
-    const int width = steps == 4 ? btrtk::batch_strip_columns() : btrtk::kTileWidth;
+    const int width = btrtk::batch_walks(steps) ? btrtk::batch_strip_columns(steps) : btrtk::kTileWidth;
     int64_t acc = 0;
     for (int i = 0; i < n; ++i) {
         begin[i] = static_cast<int>(acc);
@@ -68,13 +68,14 @@ int upload_begin(Group& g, int steps, int rows)
     return e == hipSuccess ? static_cast<int>(BTRT_OK) : hip_fail(e, "group table upload");
 }
 
-// The 4-step strip table for the configured strip height (built when first needed).
-int ensure_walk_table(Group& g)
+// The strip table of the k-step walker for the configured strip height (built when first
+// needed).
+int ensure_walk_table(Group& g, int k)
 {
     const int rows = strip_rows(g.cfg);
-    if (g.walk_rows == rows || g.inst.empty()) return BTRT_OK;
-    int rc = upload_begin(g, 4, rows);
-    if (rc == BTRT_OK) g.walk_rows = rows;
+    if (g.walk_rows[k] == rows || g.inst.empty()) return BTRT_OK;
+    int rc = upload_begin(g, k, rows);
+    if (rc == BTRT_OK) g.walk_rows[k] = rows;
     return rc;
 }
 
@@ -134,7 +135,7 @@ void fill_entries(const Group& g, std::vector<BatchEntry<T>>& ent, bool nts)
 
 bool config_ok(const btrt_batch_config_t* c)
 {
-    return c && (c->steps_per_launch == 1 || c->steps_per_launch == 2 || c->steps_per_launch == 4) &&
+    return c && btrtk::batch_steps_ok(c->steps_per_launch) &&
            c->strip_rows >= 0 && c->strip_rows <= 4096 && c->blocks_per_cu >= 0 &&
            c->blocks_per_cu <= 64 && c->graph_launches >= 0 && c->graph_launches <= 4096 &&
            (c->graph_launches == 0 || (c->graph_launches >= 2 && c->graph_launches % 2 == 0));
@@ -150,7 +151,7 @@ int group_init(Group& g, int device, hipStream_t s, int precision, int capacity)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         g.ncu = prop.multiProcessorCount;
     const size_t bytes = align_up(capacity * entry_bytes(precision)) +
-                         4 * align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
+                         6 * align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
     if (hipMalloc(reinterpret_cast<void**>(&g.tables), bytes) != hipSuccess) {
         g.tables = nullptr;
         (void)hipGetLastError();
@@ -159,12 +160,10 @@ int group_init(Group& g, int device, hipStream_t s, int precision, int capacity)
     char* t = g.tables;
     g.d_ent = t;
     t += align_up(capacity * entry_bytes(precision));
-    g.d_begin[1] = reinterpret_cast<int*>(t);
-    t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
-    g.d_begin[2] = reinterpret_cast<int*>(t);
-    t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
-    g.d_begin[4] = reinterpret_cast<int*>(t);
-    t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
+    for (int k : {1, 2, 4, 6, 7}) {
+        g.d_begin[k] = reinterpret_cast<int*>(t);
+        t += align_up(static_cast<size_t>(capacity + 1) * sizeof(int));
+    }
     g.d_par = reinterpret_cast<int*>(t);
     if (hipHostMalloc(reinterpret_cast<void**>(&g.h_res),
                       static_cast<size_t>(capacity) * kReducePartials * sizeof(double)) != hipSuccess) {
@@ -180,11 +179,11 @@ int group_upload(Group& g)
     const int n = static_cast<int>(g.inst.size());
     if (n > g.capacity) return fail(BTRT_E_INVAL, "group of %d exceeds its capacity %d", n, g.capacity);
     g.flip = 0;
-    g.walk_rows = 0;
-    if (n == 0) {
-        g.total[1] = g.total[2] = g.total[4] = 0;
-        return BTRT_OK;
+    for (int k = 0; k <= btrtk::kBatchMaxSteps; ++k) {
+        g.walk_rows[k] = 0;
+        if (n == 0) g.total[k] = 0;
     }
+    if (n == 0) return BTRT_OK;
     std::vector<int> par(n);
     hipError_t e = hipSuccess;
     for (int steps = 1; steps <= 2; ++steps) {
@@ -217,8 +216,8 @@ int group_upload(Group& g)
 int group_enqueue(Group& g, int64_t n)
 {
     if (g.inst.empty()) return BTRT_OK;
-    if (g.cfg.steps_per_launch == 4) {
-        int rc = ensure_walk_table(g);
+    if (btrtk::batch_walks(g.cfg.steps_per_launch)) {
+        int rc = ensure_walk_table(g, g.cfg.steps_per_launch);
         if (rc != BTRT_OK) return rc;
     }
     const int k = g.cfg.steps_per_launch;
@@ -283,27 +282,31 @@ int group_residuals(Group& g, double* out, int* bad)
 int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* used_out)
 {
     std::vector<btrt_batch_config_t> cand;
-    for (int rows : {16, 32})
-        for (int bpc : {0, 4})
-            for (int gl : {0, 16}) cand.push_back({4, bpc, gl, rows});
-    for (int steps : {2, 1})
-        for (int bpc : {0, 4})
-            for (int gl : {0, 16}) cand.push_back({steps, bpc, gl, 0});
-    // Each candidate: four warm-up steps, then a timed run of a multiple of 64 steps (one graph
-    // replay of 16 four-step launches).
-    const int64_t per = std::max<int64_t>(0, max_steps / static_cast<int64_t>(cand.size()) - 4) / 64 * 64;
+    for (int k : {4, 6, 7})
+        for (int rows : {16, 32}) cand.push_back({k, 0, 16, rows});
+    cand.push_back({4, 0, 0, 32});
+    cand.push_back({4, 4, 16, 32});
+    for (int gl : {0, 16}) cand.push_back({2, 0, gl, 0});
+    cand.push_back({1, 0, 16, 0});
+    // Each candidate: k warm-up steps, then a timed run of a multiple of 16 k steps (one graph
+    // replay of 16 k-step launches); candidates whose replay does not fit the share of max_steps
+    // are skipped. Compared by time per step.
+    const int64_t share = max_steps / static_cast<int64_t>(cand.size());
     const btrt_batch_config_t keep = g.cfg;
     int64_t used = 0;
     double best_ms = INFINITY;
     btrt_batch_config_t best_cfg = keep;
-    if (per > 0 && !g.inst.empty()) {
+    if (!g.inst.empty()) {
         hipEvent_t t0 = nullptr, t1 = nullptr;
         if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
             return fail(BTRT_E_DEVICE, "hipEventCreate");
         int rc = BTRT_OK;
         for (const btrt_batch_config_t& c : cand) {
+            const int k = c.steps_per_launch;
+            const int64_t per = std::max<int64_t>(0, share - k) / (16 * k) * (16 * k);
+            if (per == 0) continue;
             g.cfg = c;
-            rc = group_enqueue(g, 4);
+            rc = group_enqueue(g, k);
             if (rc == BTRT_OK && c.graph_launches > 0) rc = build_graph(g);
             if (rc != BTRT_OK) break;
             (void)hipEventRecord(t0, g.stream);
@@ -312,10 +315,10 @@ int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* 
             (void)hipEventSynchronize(t1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, t0, t1);
-            used += 4 + per;
+            used += k + per;
             if (rc != BTRT_OK) break;
-            if (ms < best_ms) {
-                best_ms = ms;
+            if (ms / per < best_ms) {
+                best_ms = ms / per;
                 best_cfg = c;
             }
         }

@@ -139,12 +139,12 @@ struct Group {
     int ncu = 256;
     int capacity = 0;
     std::vector<Instance*> inst;
-    char* tables = nullptr;  // device: entries, tile offsets (1- and 2-step tiles, 4-step strips), parities
+    char* tables = nullptr;  // device: entries, tile offsets (1- and 2-step tiles, walker strips), parities
     void* d_ent = nullptr;
-    int* d_begin[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // indexed by steps per launch
+    int* d_begin[btrtk::kBatchMaxSteps + 1] = {};  // indexed by steps per launch (1, 2, 4, 6, 7)
     int* d_par = nullptr;
-    int total[5] = {0, 0, 0, 0, 0};
-    int walk_rows = 0;  // strip height the 4-step table was built for (0: not built)
+    int total[btrtk::kBatchMaxSteps + 1] = {};
+    int walk_rows[btrtk::kBatchMaxSteps + 1] = {};  // strip height each walker table was built for (0: not built)
     int flip = 0;       // launches since group_upload, mod 2
     btrt_batch_config_t cfg{2, 0, 0, 0};
     hipGraph_t graph = nullptr;

@@ -122,13 +122,16 @@ template <typename T>
 hipError_t launch_reduce(const GatherArgs<T>& a, int fmt, int mode, double* result, hipStream_t s);
 template <typename T>
 hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, hipStream_t s);
-// All instances of a batch (plain storage) advance `steps` (1, 2 or 4) time steps in one launch
-// of `grid` blocks (0: one block per tile) walking the concatenated tile list; with 4 steps the
-// "tiles" are walker strips of batch_strip_columns() columns by `rows` rows.
+// All instances of a batch (plain storage) advance `steps` (1, 2, 4, 6 or 7) time steps in one
+// launch of `grid` blocks (0: one block per tile) walking the concatenated tile list; from 4
+// steps on the "tiles" are walker strips of batch_strip_columns(steps) columns by `rows` rows.
+constexpr bool batch_walks(int steps) { return steps == 4 || steps == 6 || steps == 7; }
+constexpr bool batch_steps_ok(int steps) { return steps == 1 || steps == 2 || batch_walks(steps); }
+constexpr int kBatchMaxSteps = 7;
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
                               int flip, int steps, int grid, int rows, hipStream_t s);
-int batch_strip_columns();
+int batch_strip_columns(int steps);
 // Tile height of the kernel that fuses `steps` steps (tile width is 64).
 int tile_rows(int steps, int precision_bytes);
 constexpr int kTileWidth = 64;

@@ -51,10 +51,11 @@ def test_batch_equals_each_instance_alone(precision):
 
 @pytest.mark.parametrize("cfg", [(1, 0, 0, 0), (2, 0, 0, 0), (2, 2, 0, 0), (1, 8, 0, 0), (2, 8, 0, 0), (2, 0, 4, 0),
                                  (1, 2, 16, 0), (2, 4, 16, 0), (4, 0, 0, 16), (4, 0, 0, 5), (4, 4, 0, 32),
-                                 (4, 2, 16, 8), (4, 0, 4, 16)], ids=lambda c: "s%d_b%d_g%d_r%d" % c)
+                                 (4, 2, 16, 8), (4, 0, 4, 16), (6, 0, 0, 16), (6, 0, 4, 32), (7, 0, 0, 16),
+                                 (7, 0, 2, 32), (7, 4, 0, 8)], ids=lambda c: "s%d_b%d_g%d_r%d" % c)
 def test_batch_configurations_bitwise_identical(cfg):
-    # 4-step strip walkers included: step counts that are not multiples of 4 end with 2- and
-    # 1-step launches; graph replays of 4-step launches; strips shorter than the instances.
+    # 4-, 6- and 7-step strip walkers included: step counts that are not multiples of k end with
+    # 2- and 1-step launches; graph replays of k-step launches; strips shorter than the instances.
     probs, _ = small_mix(count=16, seed=41)
     steps = 70
     with btrt.Batch(probs) as ref_b, btrt.Batch(probs) as b:
@@ -124,3 +125,12 @@ def test_full_batched_workload_sampled_against_alone():
         for i in (0, 1, 17, 100, 255):
             ref = alone(btrt.problem_from_workload(ws[i], precision=btrt.F32), probs[i][1], 2000)
             assert np.array_equal(b.field(i), ref), ws[i].name
+
+
+def test_batch_rejects_unsupported_steps_per_launch():
+    probs, _ = small_mix(count=4, seed=3)
+    with btrt.Batch(probs) as b:
+        for bad in (3, 5, 8, 0, -1):
+            with pytest.raises(btrt.BtrtError) as e:
+                b.set_config(bad, 0, 0)
+            assert e.value.code == btrt.E_INVAL, bad
