@@ -949,6 +949,27 @@ LaunchCfg resolve_with(const SweepArgs<typename F::T>& a, int src_kind, int kmod
     BTRT_BY_VARIANT(resolve_variant, a, cfg);
 }
 
+// k0 = 1 kernels (kK0One): the standard node model's variants with the bit set.
+#define BTRT_BY_VARIANT_K0(FN, ...)                                              \
+    do {                                                                         \
+        if ((kmode & kK1Mask) == kK1Field) BTRT_BY_SRC(kK1Field | kK0One, FN, __VA_ARGS__); \
+        if ((kmode & kK1Mask) == kK1Phi) BTRT_BY_SRC(kK1Phi | kK0One, FN, __VA_ARGS__);     \
+        BTRT_BY_SRC(kK1Const | kK0One, FN, __VA_ARGS__);                         \
+    } while (0)
+
+template <typename F>
+hipError_t sweep_with_k0(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg,
+                         hipStream_t s)
+{
+    BTRT_BY_VARIANT_K0(sweep_variant, a, cfg, s);
+}
+
+template <typename F>
+LaunchCfg resolve_with_k0(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg)
+{
+    BTRT_BY_VARIANT_K0(resolve_variant, a, cfg);
+}
+
 template <typename F>
 hipError_t sweep_with_gen(const SweepArgs<typename F::T>& a, int src_kind, int kmode, const LaunchCfg& cfg,
                           hipStream_t s)
@@ -962,6 +983,7 @@ LaunchCfg resolve_with_gen(const SweepArgs<typename F::T>& a, int src_kind, int 
     BTRT_BY_VARIANT_GEN(resolve_variant, a, cfg);
 }
 
+#undef BTRT_BY_VARIANT_K0
 #undef BTRT_BY_VARIANT_GEN
 #undef BTRT_BY_VARIANT
 #undef BTRT_BY_SRC
@@ -980,6 +1002,11 @@ LaunchCfg resolve_f16dev(const SweepArgs<float>& a, int src_kind, int kmode, con
 LaunchCfg resolve_bf16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 // The general node model (kmode carries kGen), plain storage only (btrt_sweep_gen_<format>.hip).
 hipError_t sweep_gen_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+// k0 = 1 variants of the plain formats (btrt_sweep_k0_{f64,f32}.hip).
+hipError_t sweep_k0_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+hipError_t sweep_k0_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+LaunchCfg resolve_k0_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg);
+LaunchCfg resolve_k0_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 hipError_t sweep_gen_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
 LaunchCfg resolve_gen_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 LaunchCfg resolve_gen_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);

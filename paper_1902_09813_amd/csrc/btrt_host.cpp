@@ -334,6 +334,7 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
     I.plane = static_cast<int64_t>(I.pitch) * grid->ny;
     I.kind = src_kind == BTRT_SRC_FIELD ? kSrcField : (src_kind == BTRT_SRC_SIN ? kSrcSep : kSrcNone);
     I.k1_per_node = r.k1_per_node;
+    I.k0_one = r.k0 == 1.0;
     I.afield = r.afield;
     I.growth = r.growth;
     I.gen = r.gen;

@@ -69,6 +69,7 @@ struct Instance {
     int nx = 0, ny = 0, pitch = 0, precision = 0;
     int kind = 0;         // btrtk::SrcKind of the source
     bool k1_per_node = false;
+    bool k0_one = false;  // k0 = 1 exactly: kernels without the (1 - k0) f_i term
     bool afield = false;  // per-node A0(x) planes in the workspace
     double growth = 0.0;  // source growth rate per step (Scheme 2 correction when nonzero)
     // General node model (kGen): wall table entries of 2 (nx + ny) values in the phi type; the
@@ -93,7 +94,8 @@ struct Instance {
     int kmode() const
     {
         const int k1 = afield ? btrtk::kK1Field : (k1_per_node ? btrtk::kK1Phi : btrtk::kK1Const);
-        return gen ? (k1 | btrtk::kGen) : k1;
+        if (gen) return k1 | btrtk::kGen;
+        return k0_one ? (k1 | btrtk::kK0One) : k1;
     }
     int wall_entry_values() const { return 2 * (nx + ny); }
 };

@@ -21,8 +21,12 @@ enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
 // Kernel mode = K1 mode | kGen. kGen selects the general node model: a power-law flux term
 // c |phi|^q, a source part r phi (1 - |phi|^p) that depends on phi, and Dirichlet values read
 // per boundary node and step from a wall table.
+// kK0One marks k0 = 1 exactly (the paper's choice throughout): the (1 - k0) f_i term of the
+// collision vanishes, so the populations need not stay live through it; plain FP64/FP32 storage
+// with the standard node model have such kernels, the other formats and batches ignore the bit.
 constexpr int kK1Mask = 3;
 constexpr int kGen = 4;
+constexpr int kK0One = 8;
 
 constexpr int kMaxFuse = 7;   // most time steps one sweep launch can fuse
 constexpr int kAutoFuse = 4;  // steps per launch of the automatic shape on large grids

@@ -208,10 +208,17 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode,
     if ((kmode & kGen) != 0) {  // the general node model: plain storage only
         if (fmt != kFmtPlain) return hipErrorInvalidValue;
         if constexpr (sizeof(T) == 8)
-            return sweep_gen_f64(a, src_kind, kmode, cfg, s);
+            return sweep_gen_f64(a, src_kind, kmode & ~kK0One, cfg, s);
         else
-            return sweep_gen_f32(a, src_kind, kmode, cfg, s);
+            return sweep_gen_f32(a, src_kind, kmode & ~kK0One, cfg, s);
     }
+    if ((kmode & kK0One) != 0 && fmt == kFmtPlain) {
+        if constexpr (sizeof(T) == 8)
+            return sweep_k0_f64(a, src_kind, kmode, cfg, s);
+        else
+            return sweep_k0_f32(a, src_kind, kmode, cfg, s);
+    }
+    kmode &= ~kK0One;
     if constexpr (sizeof(T) == 8) {
         if (fmt != kFmtPlain) return hipErrorInvalidValue;
         return sweep_f64(a, src_kind, kmode, cfg, s);
@@ -227,10 +234,17 @@ LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode
 {
     if ((kmode & kGen) != 0) {
         if constexpr (sizeof(T) == 8)
-            return resolve_gen_f64(a, src_kind, kmode, cfg);
+            return resolve_gen_f64(a, src_kind, kmode & ~kK0One, cfg);
         else
-            return resolve_gen_f32(a, src_kind, kmode, cfg);
+            return resolve_gen_f32(a, src_kind, kmode & ~kK0One, cfg);
     }
+    if ((kmode & kK0One) != 0 && fmt == kFmtPlain) {
+        if constexpr (sizeof(T) == 8)
+            return resolve_k0_f64(a, src_kind, kmode, cfg);
+        else
+            return resolve_k0_f32(a, src_kind, kmode, cfg);
+    }
+    kmode &= ~kK0One;
     if constexpr (sizeof(T) == 8) {
         return resolve_f64(a, src_kind, kmode, cfg);
     } else {

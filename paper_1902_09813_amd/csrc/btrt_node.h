@@ -177,6 +177,7 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
 {
     constexpr int K1M = KM & kK1Mask;
     constexpr bool GEN = (KM & kGen) != 0;
+    constexpr bool K0ONE = (KM & kK0One) != 0;  // k0 = 1: no (1 - k0) f_i term
     constexpr T third = T(1) / T(3);
     constexpr T half = T(0.5);
 
@@ -239,7 +240,7 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     }
 
     // Odd part: q = k0 j + dB - K1 (j - B + dB/2).
-    const T k0 = a.k0;
+    const T k0 = K0ONE ? T(1) : a.k0;
     const T hx = fmadd(half, dBx, jx - Bx), hy = fmadd(half, dBy, jy - By);
     const T qx = fmadd(k0, jx, dBx) - fmadd(K11, hx, K12 * hy);
     const T qy = fmadd(k0, jy, dBy) - fmadd(K12, hx, K22 * hy);
@@ -264,23 +265,25 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     const T trQ = Qxx + Qyy;
     const T base = fmadd(T(1.5), trQ, fmadd(k0, phi, s));
 
-    // f+ per direction pair: (1 - k0) f_i + w_i E_i +- 3 w_i c_i . q.
+    // f+ per direction pair: (1 - k0) f_i + w_i E_i +- 3 w_i c_i . q. With k0 = 1 the first
+    // term is dropped (fma(0, f, v) is v but for the sign of a zero v).
     const T om0 = T(1) - k0;
+    auto relax = [&](T fi, T v) { return K0ONE ? v : fmadd(om0, fi, v); };
     constexpr T w0 = Lat<T>::w0, w1 = Lat<T>::w1, w5 = Lat<T>::w5;
-    f[0] = fmadd(om0, f[0], w0 * base);
+    f[0] = relax(f[0], w0 * base);
     const T ex = w1 * fmadd(T(-4.5), Qxx, base), ox = (T(3) * w1) * qx;
-    f[1] = fmadd(om0, f[1], ex + ox);
-    f[3] = fmadd(om0, f[3], ex - ox);
+    f[1] = relax(f[1], ex + ox);
+    f[3] = relax(f[3], ex - ox);
     const T ey = w1 * fmadd(T(-4.5), Qyy, base), oy = (T(3) * w1) * qy;
-    f[2] = fmadd(om0, f[2], ey + oy);
-    f[4] = fmadd(om0, f[4], ey - oy);
+    f[2] = relax(f[2], ey + oy);
+    f[4] = relax(f[4], ey - oy);
     const T ed = fmadd(T(-4.5), trQ, base);
     const T e57 = w5 * fmadd(T(-9), Qxy, ed), o57 = (T(3) * w5) * (qx + qy);
-    f[5] = fmadd(om0, f[5], e57 + o57);
-    f[7] = fmadd(om0, f[7], e57 - o57);
+    f[5] = relax(f[5], e57 + o57);
+    f[7] = relax(f[7], e57 - o57);
     const T e68 = w5 * fmadd(T(9), Qxy, ed), o68 = (T(3) * w5) * (qy - qx);
-    f[6] = fmadd(om0, f[6], e68 + o68);
-    f[8] = fmadd(om0, f[8], e68 - o68);
+    f[6] = relax(f[6], e68 + o68);
+    f[8] = relax(f[8], e68 - o68);
     return phi;
 }
 
