@@ -30,7 +30,8 @@ METRIC = "MLUPS and % HBM roofline, batched/served vs plain; p50/p99 solve laten
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
 CSRC = os.path.join(ROOT, "paper_1902_09813_amd", "csrc")
 KERNEL_SOURCES = ("btrt_internal.h", "btrt_node.h", "btrt_device.h", "btrt_sweep_f64.hip", "btrt_sweep_f32.hip",
-                  "btrt_sweep_k0_f64.hip", "btrt_sweep_k0_f32.hip", "btrt_sweep_f16dev.hip", "btrt_sweep_bf16dev.hip",
+                  "btrt_sweep_k0_f64.hip", "btrt_sweep_k0_f32.hip", "btrt_sweep_k0_f16dev.hip",
+                  "btrt_sweep_k0_bf16dev.hip", "btrt_sweep_f16dev.hip", "btrt_sweep_bf16dev.hip",
                   "btrt_batch_kernels.hip", "btrt_kernels.hip")
 
 

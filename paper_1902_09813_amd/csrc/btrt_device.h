@@ -114,14 +114,14 @@ struct F16Codec {
     __device__ __forceinline__ static float dec(unsigned short h) { return static_cast<float>(__builtin_bit_cast(_Float16, h)); }
 };
 
-// bfloat16 (the upper half of an FP32), round to nearest even.
+// bfloat16 (the upper half of an FP32), round to nearest even. gfx950 converts in one
+// instruction (v_cvt_pk_bf16_f32); over all 2^32 FP32 inputs it gives the bits of the integer
+// rounding u + 0x7fff + (bit 16 of u), NaNs kept quiet (u | 0x400000) -- checked exhaustively on
+// the device.
 struct BF16Codec {
     __device__ __forceinline__ static unsigned short enc(float v)
     {
-        unsigned u = __builtin_bit_cast(unsigned, v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);  // NaN stays NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return static_cast<unsigned short>(u >> 16);
+        return __builtin_bit_cast(unsigned short, static_cast<__bf16>(v));
     }
     __device__ __forceinline__ static float dec(unsigned short h) { return __builtin_bit_cast(float, static_cast<unsigned>(h) << 16); }
 };
@@ -1002,9 +1002,13 @@ LaunchCfg resolve_f16dev(const SweepArgs<float>& a, int src_kind, int kmode, con
 LaunchCfg resolve_bf16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 // The general node model (kmode carries kGen), plain storage only (btrt_sweep_gen_<format>.hip).
 hipError_t sweep_gen_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
-// k0 = 1 variants of the plain formats (btrt_sweep_k0_{f64,f32}.hip).
+// k0 = 1 variants (btrt_sweep_k0_<format>.hip).
 hipError_t sweep_k0_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
 hipError_t sweep_k0_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+hipError_t sweep_k0_f16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+hipError_t sweep_k0_bf16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);
+LaunchCfg resolve_k0_f16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
+LaunchCfg resolve_k0_bf16dev(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 LaunchCfg resolve_k0_f64(const SweepArgs<double>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 LaunchCfg resolve_k0_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg);
 hipError_t sweep_gen_f32(const SweepArgs<float>& a, int src_kind, int kmode, const LaunchCfg& cfg, hipStream_t s);

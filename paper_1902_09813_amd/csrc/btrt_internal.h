@@ -22,8 +22,8 @@ enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
 // c |phi|^q, a source part r phi (1 - |phi|^p) that depends on phi, and Dirichlet values read
 // per boundary node and step from a wall table.
 // kK0One marks k0 = 1 exactly (the paper's choice throughout): the (1 - k0) f_i term of the
-// collision vanishes, so the populations need not stay live through it; plain FP64/FP32 storage
-// with the standard node model have such kernels, the other formats and batches ignore the bit.
+// collision vanishes, so the populations need not stay live through it; every storage format
+// with the standard node model has such kernels; the general node model and batches ignore the bit.
 constexpr int kK1Mask = 3;
 constexpr int kGen = 4;
 constexpr int kK0One = 8;

@@ -212,11 +212,15 @@ hipError_t launch_sweep(const SweepArgs<T>& a, int fmt, int src_kind, int kmode,
         else
             return sweep_gen_f32(a, src_kind, kmode & ~kK0One, cfg, s);
     }
-    if ((kmode & kK0One) != 0 && fmt == kFmtPlain) {
-        if constexpr (sizeof(T) == 8)
+    if ((kmode & kK0One) != 0) {
+        if constexpr (sizeof(T) == 8) {
+            if (fmt != kFmtPlain) return hipErrorInvalidValue;
             return sweep_k0_f64(a, src_kind, kmode, cfg, s);
-        else
+        } else {
+            if (fmt == kFmtF16Dev) return sweep_k0_f16dev(a, src_kind, kmode, cfg, s);
+            if (fmt == kFmtBF16Dev) return sweep_k0_bf16dev(a, src_kind, kmode, cfg, s);
             return sweep_k0_f32(a, src_kind, kmode, cfg, s);
+        }
     }
     kmode &= ~kK0One;
     if constexpr (sizeof(T) == 8) {
@@ -238,11 +242,14 @@ LaunchCfg resolve_launch(const SweepArgs<T>& a, int fmt, int src_kind, int kmode
         else
             return resolve_gen_f32(a, src_kind, kmode & ~kK0One, cfg);
     }
-    if ((kmode & kK0One) != 0 && fmt == kFmtPlain) {
-        if constexpr (sizeof(T) == 8)
+    if ((kmode & kK0One) != 0) {
+        if constexpr (sizeof(T) == 8) {
             return resolve_k0_f64(a, src_kind, kmode, cfg);
-        else
+        } else {
+            if (fmt == kFmtF16Dev) return resolve_k0_f16dev(a, src_kind, kmode, cfg);
+            if (fmt == kFmtBF16Dev) return resolve_k0_bf16dev(a, src_kind, kmode, cfg);
             return resolve_k0_f32(a, src_kind, kmode, cfg);
+        }
     }
     kmode &= ~kK0One;
     if constexpr (sizeof(T) == 8) {
