@@ -213,12 +213,15 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps);
 
 /* Shape of the sweep launches btrt_step makes. Every shape gives bitwise identical results;
  * only the speed differs. Zero fields are chosen by the library for the grid.
- *   steps_per_launch  1 .. 7 time steps per launch (0: 4 from 2^20 nodes up, else 1). With
+ *   steps_per_launch  1 .. 7 time steps per launch (0: 7 on grids periodic in x and y with
+ *                     FP64/FP32 storage and the standard node model from 2^22 nodes up, else 4
+ *                     from 2^20 nodes up, else 1). With
  *                     k >= 2 each wavefront walks a strip of 66 - 2k columns down the grid and
  *                     keeps the k - 1 intermediate time levels in registers, so the state is
  *                     read and written once per k steps. Step counts that are not a multiple of
  *                     k end with one shorter launch.
- *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size);
+ *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size, up to
+ *                     64 from six steps per launch on);
  *                     with one step per launch, the tile height 1, 2, 4, 8 or 16 (0: 4)
  *   strips_per_group  1 or 4 strips per workgroup, walked side by side in lockstep (0: auto)
  *   tile              1 with steps_per_launch 2: the two-step LDS tile kernel instead of a

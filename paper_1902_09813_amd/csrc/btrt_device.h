@@ -29,6 +29,7 @@
 #include "btrt_node.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace btrtk {
 namespace {
@@ -817,11 +818,25 @@ int walk_waves_per_cu()
 }
 
 // Automatic launch shape (measured on gfx950 over 256^2 .. 4096^2 grids):
-//  - steps: kAutoFuse (4) per launch from 2^20 nodes up (the state no longer fits the caches and the
-//    strip walkers cut its traffic), one per launch below;
-//  - strip rows: the largest of 32, 16, 8 that still gives every resident wavefront slot about
-//    two strips (rows at least 8);
-//  - strips per group: kWalkGroup with 32-row strips (large grids), else 1.
+//  - steps: kAutoDeep (7) per launch on grids periodic in x and y with plain FP64/FP32 storage
+//    and the standard node model from 2^22 nodes up (there the walkers are issue-bound and every
+//    further level saves a pass over the state: 4096^2 FP64 155k against 110k MLUPS at four
+//    steps, FP32 287k against 203k; 2048^2 FP64 120k against 93k); else kAutoFuse (4) per
+//    launch from 2^20 nodes up (the state no longer fits the caches and the strip walkers cut its
+//    traffic; walled FP64 walkers beyond four steps hold one wavefront per SIMD and lose: 4096^2
+//    91k at four steps against 73k at seven), one per launch below;
+//  - strip rows: the largest of 64 (from six steps on), 32, 16, 8 that still gives every
+//    resident wavefront slot about two strips (rows at least 8);
+//  - strips per group: from six steps on 1 (one wavefront per SIMD); else kWalkGroup with 32-row
+//    strips (large grids), else 1.
+constexpr int kAutoDeep = 7;
+
+template <typename F>
+constexpr bool plain_format()
+{
+    return std::is_same<F, Plain<typename F::T>>::value;
+}
+
 template <typename F, int SRC, int KP, int K>
 void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
 {
@@ -830,20 +845,25 @@ void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
     if (cfg.rows <= 0) {
         const int64_t want = 2LL * device_cus() * walk_waves_per_cu<F, SRC, KP, K>();
         cfg.rows = 8;
-        for (int r : {32, 16}) {
+        for (int r : {64, 32, 16}) {
+            if (r == 64 && K < 6) continue;
             if (strips_x * ((a.ny + r - 1) / r) >= want) {
                 cfg.rows = r;
                 break;
             }
         }
     }
-    if (cfg.group <= 0) cfg.group = cfg.rows >= 32 ? kWalkGroup : 1;
+    if (cfg.group <= 0) cfg.group = (K < 6 && cfg.rows >= 32) ? kWalkGroup : 1;
 }
 
 template <typename F, int SRC, int KP>
 LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
 {
-    if (cfg.steps <= 0) cfg.steps = static_cast<int64_t>(a.nx) * a.ny >= (1LL << 20) ? kAutoFuse : 1;
+    if (cfg.steps <= 0) {
+        const int64_t nodes = static_cast<int64_t>(a.nx) * a.ny;
+        const bool deep = plain_format<F>() && (KP & kGen) == 0 && a.perx && a.pery && nodes >= (1LL << 22);
+        cfg.steps = deep ? kAutoDeep : (nodes >= (1LL << 20) ? kAutoFuse : 1);
+    }
     if (cfg.steps != 2) cfg.tile = 0;
     if (cfg.steps == 1) {  // rows: tile height of the one-step kernel
         if (cfg.rows <= 0) cfg.rows = kTileY;

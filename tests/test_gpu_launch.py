@@ -79,6 +79,18 @@ def test_automatic_shape_by_grid_size():
     with btrt.Solver(btrt.problem_from_workload(w), w.phi0()) as s:
         k, rows, group, tile = s.launch()
         assert k == 4 and rows in (8, 16, 32) and group in (1, 4) and tile == 0
+    # From 2^22 nodes: seven steps per launch, one strip per group, on periodic grids with plain
+    # storage; four with Dirichlet walls or 16-bit storage.
+    big = W.c3().scaled(2048, 2048, 0)
+    for prec in (btrt.F64, btrt.F32):
+        with btrt.Solver(btrt.problem_from_workload(big, precision=prec), big.phi0()) as s:
+            k, rows, group, tile = s.launch()
+            assert k == 7 and rows in (16, 32, 64) and group == 1 and tile == 0, (prec, s.launch())
+    with btrt.Solver(btrt.problem_from_workload(big, precision=btrt.F16DEV), big.phi0()) as s:
+        assert s.launch()[0] == 4
+    walled = W.c2().scaled(2048, 2048, 0)
+    with btrt.Solver(btrt.problem_from_workload(walled), walled.phi0()) as s:
+        assert s.launch()[0] == 4
 
 
 def test_invalid_launch_shapes_are_rejected():
