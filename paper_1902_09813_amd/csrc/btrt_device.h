@@ -675,6 +675,18 @@ __device__ __forceinline__ void walk_strip(const SweepArgs<typename F::T>& a, in
 // A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
 // in one band of rows; they walk in lockstep (one barrier per row, no memory fence: they share
 // no data), so the rows they read and write at a time are contiguous across the group.
+// Whether strip (sx, sy) of a K-step walk stays clear of the grid's edges: every lane's column
+// and every row the walk loads, with their pulls at +-1, lie inside the grid, so no link wraps
+// or bounces back and the walk without wall handling computes the same bits.
+template <int K, typename T>
+__device__ __forceinline__ bool walk_clear_of_edges(const SweepArgs<T>& a, int sx, int sy)
+{
+    const int cx0 = sx * Walk<K>::W - (K - 1);
+    const int ys = sy * a.rows;
+    const int ye = min(ys + a.rows, a.ny);
+    return cx0 >= 1 && cx0 + kWave - 1 <= a.nx - 2 && ys - K >= 0 && ye + K - 1 <= a.ny - 1;
+}
+
 template <typename F, int SRC, int KM, int K, bool WALLS>
 __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typename F::T> a)
 {
@@ -683,7 +695,18 @@ __global__ __launch_bounds__(kWave* kWalkGroup) void walk_kernel(SweepArgs<typen
     const int groups_x = (a.tiles_x + gsize - 1) / gsize;
     const int sy = group / groups_x;
     const int sx = (group - sy * groups_x) * gsize + static_cast<int>(threadIdx.x / kWave);
-    walk_strip<F, SRC, KM, K, WALLS>(a, sx, sy, sx < a.tiles_x, static_cast<int>(threadIdx.x % kWave));
+    const bool live = sx < a.tiles_x;
+    const int lane = static_cast<int>(threadIdx.x % kWave);
+    if constexpr (WALLS) {
+        // Strips away from every edge (almost all of a large grid) skip the bounce-back code;
+        // the choice is uniform per wavefront, and both walks meet the group's barriers row by
+        // row alike.
+        if (live && walk_clear_of_edges<K>(a, sx, sy)) {
+            walk_strip<F, SRC, KM, K, false>(a, sx, sy, true, lane);
+            return;
+        }
+    }
+    walk_strip<F, SRC, KM, K, WALLS>(a, sx, sy, live, lane);
 }
 
 // ---- many instances in one launch -------------------------------------------------------
