@@ -140,8 +140,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                              "python paper_1902_09813_amd/build.py")
+            raise ImportError(f"{LIB_PATH} is not built; run python paper_1902_09813_amd/build.py")
         # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname). Loading
         # torch first makes libbtrt bind to that copy, so device pointers and streams handed
         # over from torch belong to the runtime the library launches on. Without torch the
