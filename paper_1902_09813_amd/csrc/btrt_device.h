@@ -726,7 +726,7 @@ __device__ __forceinline__ int owner(const int* __restrict__ begin, int ninst, i
     return lo;
 }
 
-template <typename T>
+template <typename T, int K0>
 __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __restrict__ ent,
                                                         const int* __restrict__ begin, const int* __restrict__ par,
                                                         int ninst, int total, int flip)
@@ -740,17 +740,17 @@ __global__ __launch_bounds__(kBlock) void batch1_kernel(const BatchEntry<T>* __r
         const int tiles_x = (a.nx + kTileX - 1) / kTileX;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile1<F, kSrcNone, kK1Const>(a, tx, ty, kTileY); break;
-            case 1: tile1<F, kSrcNone, kK1Phi>(a, tx, ty, kTileY); break;
-            case 2: tile1<F, kSrcField, kK1Const>(a, tx, ty, kTileY); break;
-            case 3: tile1<F, kSrcField, kK1Phi>(a, tx, ty, kTileY); break;
-            case 4: tile1<F, kSrcSep, kK1Const>(a, tx, ty, kTileY); break;
-            default: tile1<F, kSrcSep, kK1Phi>(a, tx, ty, kTileY); break;
+            case 0: tile1<F, kSrcNone, kK1Const | K0>(a, tx, ty, kTileY); break;
+            case 1: tile1<F, kSrcNone, kK1Phi | K0>(a, tx, ty, kTileY); break;
+            case 2: tile1<F, kSrcField, kK1Const | K0>(a, tx, ty, kTileY); break;
+            case 3: tile1<F, kSrcField, kK1Phi | K0>(a, tx, ty, kTileY); break;
+            case 4: tile1<F, kSrcSep, kK1Const | K0>(a, tx, ty, kTileY); break;
+            default: tile1<F, kSrcSep, kK1Phi | K0>(a, tx, ty, kTileY); break;
         }
     }
 }
 
-template <typename T>
+template <typename T, int K0>
 __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __restrict__ ent,
                                                          const int* __restrict__ begin, const int* __restrict__ par,
                                                          int ninst, int total, int flip)
@@ -766,12 +766,12 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
         const int tiles_x = (a.nx + kTile2X - 1) / kTile2X;
         const int ty = local / tiles_x, tx = local - ty * tiles_x;
         switch (ent[i].variant) {
-            case 0: tile2<F, kSrcNone, kK1Const>(a, tx, ty, lf, lphi); break;
-            case 1: tile2<F, kSrcNone, kK1Phi>(a, tx, ty, lf, lphi); break;
-            case 2: tile2<F, kSrcField, kK1Const>(a, tx, ty, lf, lphi); break;
-            case 3: tile2<F, kSrcField, kK1Phi>(a, tx, ty, lf, lphi); break;
-            case 4: tile2<F, kSrcSep, kK1Const>(a, tx, ty, lf, lphi); break;
-            default: tile2<F, kSrcSep, kK1Phi>(a, tx, ty, lf, lphi); break;
+            case 0: tile2<F, kSrcNone, kK1Const | K0>(a, tx, ty, lf, lphi); break;
+            case 1: tile2<F, kSrcNone, kK1Phi | K0>(a, tx, ty, lf, lphi); break;
+            case 2: tile2<F, kSrcField, kK1Const | K0>(a, tx, ty, lf, lphi); break;
+            case 3: tile2<F, kSrcField, kK1Phi | K0>(a, tx, ty, lf, lphi); break;
+            case 4: tile2<F, kSrcSep, kK1Const | K0>(a, tx, ty, lf, lphi); break;
+            default: tile2<F, kSrcSep, kK1Phi | K0>(a, tx, ty, lf, lphi); break;
         }
         __syncthreads();  // the next tile reuses the LDS
     }
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(kBlock2) void batch2_kernel(const BatchEntry<T>* __
 
 // Four steps per launch for a batch: the strips of every instance (58 columns by `rows` rows)
 // form the list; one wavefront per strip, no lockstep groups (instances differ in length).
-template <typename T, int K>
+template <typename T, int K, int K0>
 __global__ __launch_bounds__(kWave) void batchw_kernel(const BatchEntry<T>* __restrict__ ent,
                                                        const int* __restrict__ begin, const int* __restrict__ par,
                                                        int ninst, int total, int flip, int rows)
@@ -796,18 +796,18 @@ __global__ __launch_bounds__(kWave) void batchw_kernel(const BatchEntry<T>* __re
         const int sy = local / a.tiles_x, sx = local - sy * a.tiles_x;
         const bool walls = !(a.perx && a.pery);
         switch (2 * ent[i].variant + (walls ? 1 : 0)) {
-            case 0: walk_strip<F, kSrcNone, kK1Const, K, false>(a, sx, sy, true, lane); break;
-            case 1: walk_strip<F, kSrcNone, kK1Const, K, true>(a, sx, sy, true, lane); break;
-            case 2: walk_strip<F, kSrcNone, kK1Phi, K, false>(a, sx, sy, true, lane); break;
-            case 3: walk_strip<F, kSrcNone, kK1Phi, K, true>(a, sx, sy, true, lane); break;
-            case 4: walk_strip<F, kSrcField, kK1Const, K, false>(a, sx, sy, true, lane); break;
-            case 5: walk_strip<F, kSrcField, kK1Const, K, true>(a, sx, sy, true, lane); break;
-            case 6: walk_strip<F, kSrcField, kK1Phi, K, false>(a, sx, sy, true, lane); break;
-            case 7: walk_strip<F, kSrcField, kK1Phi, K, true>(a, sx, sy, true, lane); break;
-            case 8: walk_strip<F, kSrcSep, kK1Const, K, false>(a, sx, sy, true, lane); break;
-            case 9: walk_strip<F, kSrcSep, kK1Const, K, true>(a, sx, sy, true, lane); break;
-            case 10: walk_strip<F, kSrcSep, kK1Phi, K, false>(a, sx, sy, true, lane); break;
-            default: walk_strip<F, kSrcSep, kK1Phi, K, true>(a, sx, sy, true, lane); break;
+            case 0: walk_strip<F, kSrcNone, kK1Const | K0, K, false>(a, sx, sy, true, lane); break;
+            case 1: walk_strip<F, kSrcNone, kK1Const | K0, K, true>(a, sx, sy, true, lane); break;
+            case 2: walk_strip<F, kSrcNone, kK1Phi | K0, K, false>(a, sx, sy, true, lane); break;
+            case 3: walk_strip<F, kSrcNone, kK1Phi | K0, K, true>(a, sx, sy, true, lane); break;
+            case 4: walk_strip<F, kSrcField, kK1Const | K0, K, false>(a, sx, sy, true, lane); break;
+            case 5: walk_strip<F, kSrcField, kK1Const | K0, K, true>(a, sx, sy, true, lane); break;
+            case 6: walk_strip<F, kSrcField, kK1Phi | K0, K, false>(a, sx, sy, true, lane); break;
+            case 7: walk_strip<F, kSrcField, kK1Phi | K0, K, true>(a, sx, sy, true, lane); break;
+            case 8: walk_strip<F, kSrcSep, kK1Const | K0, K, false>(a, sx, sy, true, lane); break;
+            case 9: walk_strip<F, kSrcSep, kK1Const | K0, K, true>(a, sx, sy, true, lane); break;
+            case 10: walk_strip<F, kSrcSep, kK1Phi | K0, K, false>(a, sx, sy, true, lane); break;
+            default: walk_strip<F, kSrcSep, kK1Phi | K0, K, true>(a, sx, sy, true, lane); break;
         }
     }
 }

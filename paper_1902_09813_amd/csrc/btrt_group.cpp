@@ -38,12 +38,14 @@ hipError_t raw_launch(Group& g, int steps, int flip)
 {
     const int n = static_cast<int>(g.inst.size());
     const int rows = strip_rows(g.cfg);
+    bool k0one = true;
+    for (const Instance* I : g.inst) k0one = k0one && I->k0_one;
     if (g.precision == BTRT_F64)
         return btrtk::launch_batch_sweep<double>(static_cast<const BatchEntry<double>*>(g.d_ent), g.d_begin[steps],
-                                                 g.d_par, n, g.total[steps], flip, steps, grid_blocks(g), rows,
+                                                 g.d_par, n, g.total[steps], flip, steps, grid_blocks(g), rows, k0one,
                                                  g.stream);
     return btrtk::launch_batch_sweep<float>(static_cast<const BatchEntry<float>*>(g.d_ent), g.d_begin[steps], g.d_par,
-                                            n, g.total[steps], flip, steps, grid_blocks(g), rows, g.stream);
+                                            n, g.total[steps], flip, steps, grid_blocks(g), rows, k0one, g.stream);
 }
 
 // Offsets of each member's units in the concatenated list for `steps` per launch: 64 x rows

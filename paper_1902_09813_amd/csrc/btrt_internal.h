@@ -23,7 +23,8 @@ enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
 // per boundary node and step from a wall table.
 // kK0One marks k0 = 1 exactly (the paper's choice throughout): the (1 - k0) f_i term of the
 // collision vanishes, so the populations need not stay live through it; every storage format
-// with the standard node model has such kernels; the general node model and batches ignore the bit.
+// with the standard node model has such kernels, and batches whose instances all have k0 = 1;
+// the general node model ignores the bit.
 constexpr int kK1Mask = 3;
 constexpr int kGen = 4;
 constexpr int kK0One = 8;
@@ -129,12 +130,13 @@ hipError_t launch_convert(const double* in, T* out, int nx, int ny, int pitch, h
 // All instances of a batch (plain storage) advance `steps` (1, 2, 4, 6 or 7) time steps in one
 // launch of `grid` blocks (0: one block per tile) walking the concatenated tile list; from 4
 // steps on the "tiles" are walker strips of batch_strip_columns(steps) columns by `rows` rows.
+// k0one: every instance has k0 = 1 (the kK0One kernels, the bits of the single solves).
 constexpr bool batch_walks(int steps) { return steps == 4 || steps == 6 || steps == 7; }
 constexpr bool batch_steps_ok(int steps) { return steps == 1 || steps == 2 || batch_walks(steps); }
 constexpr int kBatchMaxSteps = 7;
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
-                              int flip, int steps, int grid, int rows, hipStream_t s);
+                              int flip, int steps, int grid, int rows, bool k0one, hipStream_t s);
 int batch_strip_columns(int steps);
 // Tile height of the kernel that fuses `steps` steps (tile width is 64).
 int tile_rows(int steps, int precision_bytes);
