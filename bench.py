@@ -315,9 +315,9 @@ def traffic_key(precision_name, launch):
             f"_g{launch['strips_per_group']}_t{launch['tile']}")
 
 
-def traffic_for(precision_name, nodes, launch):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None if the
-    kernel source changed since the counters were taken or that shape was not measured."""
+def counter_record(precision_name, nodes, launch):
+    """The committed rocprofv3 counter figures of one launch shape, or None if the kernel source
+    changed since the counters were taken or that shape was not measured on this grid."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -328,7 +328,20 @@ def traffic_for(precision_name, nodes, launch):
     ent = rec.get(traffic_key(precision_name, launch))
     if not ent or ent.get("nodes") != nodes:
         return None
-    return ent.get("bytes_per_launch")
+    return ent
+
+
+def traffic_for(precision_name, nodes, launch):
+    """HBM bytes per sweep launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None."""
+    ent = counter_record(precision_name, nodes, launch)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def valu_busy_for(precision_name, nodes, launch):
+    """Fraction of SIMD cycles with a VALU instruction in flight (SQ_ACTIVE_INST_VALU x 4 over
+    1024 SIMDs x GRBM_GUI_ACTIVE per XCD), or None if not measured for this shape and source."""
+    ent = counter_record(precision_name, nodes, launch)
+    return None if ent is None else ent.get("valu_busy")
 
 
 def copy_probe(nbytes):
@@ -408,6 +421,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic_for(args.precision, r["nodes"], r["launch"]),
+        "valu_busy": valu_busy_for(args.precision, r["nodes"], r["launch"]),
         "bytes_per_launch": bytes_per_launch,
         "launch": r["launch"],
         "launch_us_avg": round(r["launch_ms_avg"] * 1e3, 2),

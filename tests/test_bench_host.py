@@ -42,6 +42,9 @@ def test_traffic_record_lookup():
     got = bench.traffic_for("f64", nodes, shape)
     alg = 160 * nodes
     assert got is not None and alg <= got <= 1.3 * alg
+    busy = bench.valu_busy_for("f64", nodes, shape)
+    assert busy is not None and 0.0 < busy <= 1.0
+    assert bench.valu_busy_for("f64", nodes, dict(shape, strip_rows=8)) is None
     assert bench.traffic_for("f64", nodes + 1, shape) is None  # another grid
     assert bench.traffic_for("f64", nodes, dict(shape, strip_rows=8)) is None  # a shape not measured
     assert bench.traffic_key("f32", dict(steps_per_launch=4, strip_rows=32, strips_per_group=4, tile=0)) == \
