@@ -296,6 +296,10 @@ void fill_constants(Instance& I, SweepArgs<T>& a, const btrt_flux_t* B, const bt
     a.k2xx = static_cast<T>(r.K2[0]);
     a.k2xy = static_cast<T>(0.5 * (r.K2[1] + r.K2[2]));
     a.k2yy = static_cast<T>(r.K2[3]);
+    a.cq[0] = T(1.5);
+    a.cq[1] = T(-4.5);
+    a.cq[2] = T(-9);
+    a.cq[3] = T(9);
     a.src_amp = static_cast<T>(R && R->kind == BTRT_SRC_SIN ? R->amp : 0.0);
     a.src = I.kind == kSrcNone ? nullptr : reinterpret_cast<const T*>(I.mem + I.L.src);
     a.src_y = I.kind == kSrcSep ? reinterpret_cast<const T*>(I.mem + I.L.src_y) : nullptr;

@@ -49,6 +49,9 @@ struct SweepArgs {
     T a11, a12, a22, beta; // A(phi) = A0 (1 + beta phi^2), used when K1 is per node
     T K11, K12, K22;   // K1 of Eq. (30) when A is constant
     T k0, k2xx, k2xy, k2yy;
+    T cq[4];           // the collision's constants 3/2, -9/2, -9, 9 (read from the arguments, the
+                       // kernels keep them in scalar registers instead of copying an accumulator
+                       // for every multiply-add with an inline constant)
     T src_amp;
     T sfac[kMaxFuse];  // source factor of each step of the launch (1: time independent)
     T fcx, fcy, fq;    // kGen: B(phi) gains (fcx, fcy) |phi|^fq

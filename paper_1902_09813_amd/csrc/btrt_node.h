@@ -263,7 +263,9 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
         Qyy = Qyy + diag;
     }
     const T trQ = Qxx + Qyy;
-    const T base = fmadd(T(1.5), trQ, fmadd(k0, phi, s));
+    // Without a source s is zero, and k0 phi is the product itself (no "+ 0" instruction).
+    const T ks = (SRC == kSrcNone && !GEN) ? k0 * phi : fmadd(k0, phi, s);
+    const T base = fmadd(a.cq[0], trQ, ks);
 
     // f+ per direction pair: (1 - k0) f_i + w_i E_i +- 3 w_i c_i . q. With k0 = 1 the first
     // term is dropped (fma(0, f, v) is v but for the sign of a zero v).
@@ -271,17 +273,17 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
     auto relax = [&](T fi, T v) { return K0ONE ? v : fmadd(om0, fi, v); };
     constexpr T w0 = Lat<T>::w0, w1 = Lat<T>::w1, w5 = Lat<T>::w5;
     f[0] = relax(f[0], w0 * base);
-    const T ex = w1 * fmadd(T(-4.5), Qxx, base), ox = (T(3) * w1) * qx;
+    const T ex = w1 * fmadd(a.cq[1], Qxx, base), ox = (T(3) * w1) * qx;
     f[1] = relax(f[1], ex + ox);
     f[3] = relax(f[3], ex - ox);
-    const T ey = w1 * fmadd(T(-4.5), Qyy, base), oy = (T(3) * w1) * qy;
+    const T ey = w1 * fmadd(a.cq[1], Qyy, base), oy = (T(3) * w1) * qy;
     f[2] = relax(f[2], ey + oy);
     f[4] = relax(f[4], ey - oy);
-    const T ed = fmadd(T(-4.5), trQ, base);
-    const T e57 = w5 * fmadd(T(-9), Qxy, ed), o57 = (T(3) * w5) * (qx + qy);
+    const T ed = fmadd(a.cq[1], trQ, base);
+    const T e57 = w5 * fmadd(a.cq[2], Qxy, ed), o57 = (T(3) * w5) * (qx + qy);
     f[5] = relax(f[5], e57 + o57);
     f[7] = relax(f[7], e57 - o57);
-    const T e68 = w5 * fmadd(T(9), Qxy, ed), o68 = (T(3) * w5) * (qy - qx);
+    const T e68 = w5 * fmadd(a.cq[3], Qxy, ed), o68 = (T(3) * w5) * (qy - qx);
     f[6] = relax(f[6], e68 + o68);
     f[8] = relax(f[8], e68 - o68);
     return phi;
