@@ -222,6 +222,8 @@ void fill3(btrt3* h, Sweep3<T>& a, const btrt3_flux_t* B, const btrt3_diff_t* K,
     const double k1s[6] = {r.K1[0], r.K1[1], r.K1[2], r.K1[4], r.K1[5], r.K1[8]};
     for (int c = 0; c < 6; ++c) a.K1[c] = static_cast<T>(k1s[c]);
     a.k0 = static_cast<T>(r.k0);
+    const double cq[6] = {1.5, -4.5, 3.0, -3.0, 9.0, -9.0};
+    for (int c = 0; c < 6; ++c) a.cq[c] = static_cast<T>(cq[c]);
     const double* k2 = r.K2;
     const double q2[6] = {k2[0], 0.5 * (k2[1] + k2[3]), 0.5 * (k2[2] + k2[6]), k2[4], 0.5 * (k2[5] + k2[7]), k2[8]};
     for (int c = 0; c < 6; ++c) a.q2[c] = static_cast<T>(q2[c]);

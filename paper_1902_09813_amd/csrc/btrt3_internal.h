@@ -28,6 +28,9 @@ struct Sweep3 {
     T beta;
     T K1[6];            // constant K1 (symmetric) in the same order
     T k0;
+    T cq[6];            // the collision's constants 3/2, -9/2, 3, -3, 9, -9 (from the arguments the
+                        // kernels keep them in scalar registers, so a multiply-add needs no copy of
+                        // its accumulator)
     T q2[6];            // K2 rates (k2_11, k2_12s, k2_13s, k2_22, k2_23s, k2_33), off-diagonals
                         // symmetrised (Eq. (100))
     int tiles_x, tiles_y;

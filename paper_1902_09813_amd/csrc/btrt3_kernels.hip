@@ -179,36 +179,36 @@ __device__ __forceinline__ T collide3(const Sweep3<T>& a, T f[kQ], T phi_prev, T
     const T Qxx = (a.q2[0] - a.k0) * (pxx - phi3), Qyy = (a.q2[3] - a.k0) * (pyy - phi3);
     const T Qzz = (a.q2[5] - a.k0) * (pzz - phi3);
     const T Qxy = (a.q2[1] - a.k0) * pxy, Qxz = (a.q2[2] - a.k0) * pxz, Qyz = (a.q2[4] - a.k0) * pyz;
-    const T E0 = fmadd(T(1.5), (Qxx + Qyy) + Qzz, fmadd(a.k0, phi, s));
+    const T E0 = fmadd(a.cq[0], (Qxx + Qyy) + Qzz, fmadd(a.k0, phi, s));
 
     const T om = T(1) - a.k0;
     const T w0 = wv<T>(0), w1 = wv<T>(1), w2 = wv<T>(7);
     f[0] = fmadd(om, f[0], w0 * E0);
     // Axis pairs: c^T Q c = Q_aa, c . q = +-q_a.
-    const T ex = fmadd(T(-4.5), Qxx, E0), ey = fmadd(T(-4.5), Qyy, E0), ez = fmadd(T(-4.5), Qzz, E0);
-    f[1] = fmadd(om, f[1], w1 * fmadd(T(3), qx, ex));
-    f[2] = fmadd(om, f[2], w1 * fmadd(T(-3), qx, ex));
-    f[3] = fmadd(om, f[3], w1 * fmadd(T(3), qy, ey));
-    f[4] = fmadd(om, f[4], w1 * fmadd(T(-3), qy, ey));
-    f[5] = fmadd(om, f[5], w1 * fmadd(T(3), qz, ez));
-    f[6] = fmadd(om, f[6], w1 * fmadd(T(-3), qz, ez));
+    const T ex = fmadd(a.cq[1], Qxx, E0), ey = fmadd(a.cq[1], Qyy, E0), ez = fmadd(a.cq[1], Qzz, E0);
+    f[1] = fmadd(om, f[1], w1 * fmadd(a.cq[2], qx, ex));
+    f[2] = fmadd(om, f[2], w1 * fmadd(a.cq[3], qx, ex));
+    f[3] = fmadd(om, f[3], w1 * fmadd(a.cq[2], qy, ey));
+    f[4] = fmadd(om, f[4], w1 * fmadd(a.cq[3], qy, ey));
+    f[5] = fmadd(om, f[5], w1 * fmadd(a.cq[2], qz, ez));
+    f[6] = fmadd(om, f[6], w1 * fmadd(a.cq[3], qz, ez));
     // Face-diagonal pairs: c^T Q c = Q_aa + Q_bb +- 2 Q_ab, c . q = +-q_a +- q_b.
-    const T xy = fmadd(T(-4.5), Qxx + Qyy, E0), xz = fmadd(T(-4.5), Qxx + Qzz, E0), yz = fmadd(T(-4.5), Qyy + Qzz, E0);
-    const T xyp = fmadd(T(-9), Qxy, xy), xym = fmadd(T(9), Qxy, xy);
-    const T xzp = fmadd(T(-9), Qxz, xz), xzm = fmadd(T(9), Qxz, xz);
-    const T yzp = fmadd(T(-9), Qyz, yz), yzm = fmadd(T(9), Qyz, yz);
-    f[7] = fmadd(om, f[7], w2 * fmadd(T(3), qx + qy, xyp));    // ( 1,  1,  0)
-    f[10] = fmadd(om, f[10], w2 * fmadd(T(-3), qx + qy, xyp)); // (-1, -1,  0)
-    f[8] = fmadd(om, f[8], w2 * fmadd(T(3), qy - qx, xym));    // (-1,  1,  0)
-    f[9] = fmadd(om, f[9], w2 * fmadd(T(-3), qy - qx, xym));   // ( 1, -1,  0)
-    f[11] = fmadd(om, f[11], w2 * fmadd(T(3), qx + qz, xzp));  // ( 1,  0,  1)
-    f[14] = fmadd(om, f[14], w2 * fmadd(T(-3), qx + qz, xzp)); // (-1,  0, -1)
-    f[12] = fmadd(om, f[12], w2 * fmadd(T(3), qz - qx, xzm));  // (-1,  0,  1)
-    f[13] = fmadd(om, f[13], w2 * fmadd(T(-3), qz - qx, xzm)); // ( 1,  0, -1)
-    f[15] = fmadd(om, f[15], w2 * fmadd(T(3), qy + qz, yzp));  // ( 0,  1,  1)
-    f[18] = fmadd(om, f[18], w2 * fmadd(T(-3), qy + qz, yzp)); // ( 0, -1, -1)
-    f[16] = fmadd(om, f[16], w2 * fmadd(T(3), qz - qy, yzm));  // ( 0, -1,  1)
-    f[17] = fmadd(om, f[17], w2 * fmadd(T(-3), qz - qy, yzm)); // ( 0,  1, -1)
+    const T xy = fmadd(a.cq[1], Qxx + Qyy, E0), xz = fmadd(a.cq[1], Qxx + Qzz, E0), yz = fmadd(a.cq[1], Qyy + Qzz, E0);
+    const T xyp = fmadd(a.cq[5], Qxy, xy), xym = fmadd(a.cq[4], Qxy, xy);
+    const T xzp = fmadd(a.cq[5], Qxz, xz), xzm = fmadd(a.cq[4], Qxz, xz);
+    const T yzp = fmadd(a.cq[5], Qyz, yz), yzm = fmadd(a.cq[4], Qyz, yz);
+    f[7] = fmadd(om, f[7], w2 * fmadd(a.cq[2], qx + qy, xyp));    // ( 1,  1,  0)
+    f[10] = fmadd(om, f[10], w2 * fmadd(a.cq[3], qx + qy, xyp)); // (-1, -1,  0)
+    f[8] = fmadd(om, f[8], w2 * fmadd(a.cq[2], qy - qx, xym));    // (-1,  1,  0)
+    f[9] = fmadd(om, f[9], w2 * fmadd(a.cq[3], qy - qx, xym));   // ( 1, -1,  0)
+    f[11] = fmadd(om, f[11], w2 * fmadd(a.cq[2], qx + qz, xzp));  // ( 1,  0,  1)
+    f[14] = fmadd(om, f[14], w2 * fmadd(a.cq[3], qx + qz, xzp)); // (-1,  0, -1)
+    f[12] = fmadd(om, f[12], w2 * fmadd(a.cq[2], qz - qx, xzm));  // (-1,  0,  1)
+    f[13] = fmadd(om, f[13], w2 * fmadd(a.cq[3], qz - qx, xzm)); // ( 1,  0, -1)
+    f[15] = fmadd(om, f[15], w2 * fmadd(a.cq[2], qy + qz, yzp));  // ( 0,  1,  1)
+    f[18] = fmadd(om, f[18], w2 * fmadd(a.cq[3], qy + qz, yzp)); // ( 0, -1, -1)
+    f[16] = fmadd(om, f[16], w2 * fmadd(a.cq[2], qz - qy, yzm));  // ( 0, -1,  1)
+    f[17] = fmadd(om, f[17], w2 * fmadd(a.cq[3], qz - qy, yzm)); // ( 0,  1, -1)
     return phi;
 }
 
