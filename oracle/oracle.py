@@ -13,7 +13,7 @@ solutions used as pins:
 * ``gaussian_hill``        Eq. (71), the anisotropic Gaussian hill (with periodic images).
 * ``source_sin``           the separable sinusoidal source of the benchmark problems.
 * ``burgers_fisher``       Eqs. (68)-(69), the travelling wave of the Burgers-Fisher equation.
-* ``WallLinks``            per-link Dirichlet values from values along each side.
+* ``WallLinks``            per-link Dirichlet values at the points where links cross the walls.
 
 Nothing here imports the product package.
 """
@@ -300,13 +300,21 @@ def burgers_fisher(X, Y, t: float, a: float, alpha: float, b: float, delta: floa
 
 
 class WallLinks:
-    """Per-link Dirichlet values (9, ny, nx) for orc_run from values along the sides.
+    """Per-link Dirichlet values (9, ny, nx) for orc_run from values sampled along the sides.
 
-    The sides are given as one vector v of 2 (nx + ny) values: x- at rows j (v[j]), x+ at
-    rows j (v[ny + j]), y- at columns i (v[2 ny + i]), y+ at columns i (v[2 ny + nx + i]).
-    A link of node (i, j) leaving through side x- or x+ takes that side's value at row j,
-    through y- or y+ the value at column i, and a diagonal link leaving through a corner point
-    the mean of the two (Eqs. (54)-(56) with a wall value that varies along the side).
+    Half-way bounce-back (Eqs. (54)-(56)) puts the wall half a lattice spacing beyond the last
+    node, so the link from node x along c_i meets it at x + c_i/2. With the node of column i at
+    i + 1/2 (and of row j at j + 1/2), the points where links meet a side lie at half-integer
+    and integer positions along it: a side of n nodes carries 2n + 1 samples, sample s at
+    position s/2 measured from the side's lower corner (odd s: level with a node; even s: between
+    two nodes; s = 0 and s = 2n: the corners). The vector v holds, in order, x- (2 ny + 1 samples
+    along y), x+ (2 ny + 1), y- (2 nx + 1 samples along x), y+ (2 nx + 1).
+
+    The link from node (i, j) along c = (cx, cy) that leaves through x- or x+ takes that side's
+    sample 2 j + 1 + cy; through y- or y+, the sample 2 i + 1 + cx. A diagonal link from a corner
+    node that leaves through both (it meets the corner point) takes the mean of the two sides'
+    corner samples, which is the corner value itself when the two sides agree there and the mean
+    of the two sides for unequal constant sides.
     """
 
     CX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
@@ -315,20 +323,23 @@ class WallLinks:
     def __init__(self, nx: int, ny: int, bc_type: Sequence[int]):
         self.nx, self.ny = nx, ny
         perx, pery = bc_type[0] == PERIODIC, bc_type[2] == PERIODIC
+        base = {"x-": 0, "x+": 2 * ny + 1, "y-": 2 * (2 * ny + 1), "y+": 2 * (2 * ny + 1) + 2 * nx + 1}
         links, ia, ib = [], [], []
         edge = sorted({(i, j) for j in range(ny) for i in (0, nx - 1)}
                       | {(i, j) for i in range(nx) for j in (0, ny - 1)}, key=lambda q: (q[1], q[0]))
         for k in range(1, 9):
+            cx, cy = self.CX[k], self.CY[k]
             for i, j in edge:
-                outx = not perx and not (0 <= i + self.CX[k] < nx)
-                outy = not pery and not (0 <= j + self.CY[k] < ny)
+                outx = not perx and not (0 <= i + cx < nx)
+                outy = not pery and not (0 <= j + cy < ny)
                 if not (outx or outy):
                     continue
-                vx = (j if self.CX[k] < 0 else ny + j) if outx else -1
-                vy = (2 * ny + i if self.CY[k] < 0 else 2 * ny + nx + i) if outy else -1
+                sx = base["x-" if cx < 0 else "x+"] + 2 * j + 1 + cy if outx else -1
+                sy = base["y-" if cy < 0 else "y+"] + 2 * i + 1 + cx if outy else -1
                 links.append((k * ny + j) * nx + i)
-                ia.append(vx if outx else vy)
-                ib.append(vy if outy else vx)
+                ia.append(sx if outx else sy)
+                ib.append(sy if outy else sx)
+        self.size = 4 * (nx + ny) + 4
         self.links = np.asarray(links, dtype=np.int64)
         self.ia = np.asarray(ia, dtype=np.int64)
         self.ib = np.asarray(ib, dtype=np.int64)
@@ -336,7 +347,17 @@ class WallLinks:
 
     def __call__(self, v: np.ndarray) -> np.ndarray:
         v = np.asarray(v, dtype=np.float64)
-        assert v.shape == (2 * (self.nx + self.ny),)
+        assert v.shape == (self.size,)
         flat = self.out.reshape(-1)
         flat[self.links] = 0.5 * (v[self.ia] + v[self.ib])
         return self.out
+
+    def positions(self):
+        """Lattice coordinates (x, y) of the 4 (nx + ny) + 4 samples of v, in v's order (walls at
+        0 and nx, 0 and ny; nodes at i + 1/2)."""
+        nx, ny = self.nx, self.ny
+        sy = np.arange(2 * ny + 1) / 2.0
+        sx = np.arange(2 * nx + 1) / 2.0
+        xs = np.concatenate([np.zeros_like(sy), np.full_like(sy, nx), sx, sx])
+        ys = np.concatenate([sy, sy, np.zeros_like(sx), np.full_like(sx, ny)])
+        return xs, ys

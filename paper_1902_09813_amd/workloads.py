@@ -38,7 +38,8 @@ Workloads (lattice units; the paper's problems are analytic, so no dataset is in
           delta = 1.5 unless given: in lattice units B(phi) = (a / ((delta + 1) c)) |phi|^(delta+1)
           along x, A = alpha dt / dx^2 I, S(phi) = b dt phi (1 - |phi|^delta), k0 = 1, k2 from
           Eq. (62); phi0 and the Dirichlet values on all four walls from Eq. (68), the walls at
-          time (k + 1) dt for the k-th step.
+          time (k + 1) dt for the k-th step, sampled where the links meet them (every half
+          lattice spacing along each side, corners included).
 
 * ``d3``   three-dimensional (D3Q19) problems: ``d3_hill(n)`` an n^3 periodic box, anisotropic
           A0 = [[0.05, 0.01, 0.005], [0.01, 0.04, -0.008], [0.005, -0.008, 0.03]], B = phi u with
@@ -89,7 +90,9 @@ class Workload:
     src_r: float = 0.0                      # S gains r phi (1 - |phi|^p)
     src_p: float = 1.0
     walls: Optional[Callable[[int], np.ndarray]] = None  # k -> Dirichlet values of the k-th step
-    #                                         along the sides: x- (ny), x+ (ny), y- (nx), y+ (nx)
+    #                                         at the points where links meet the sides, every half
+    #                                         lattice spacing from corner to corner: x- (2 ny + 1),
+    #                                         x+ (2 ny + 1), y- (2 nx + 1), y+ (2 nx + 1)
     dterm: Optional[Tuple[float, float, float]] = None  # D = (g phi + e |phi|^s) I; None: D = phi I
 
     def phi0(self) -> np.ndarray:
@@ -150,22 +153,26 @@ def bfe(n: int = 40, alpha: float = 0.05, a: float = 2.0, b: float = 0.05, delta
     dx = 1.0 / n
     dt = dx / c
     m = 3 * n
-    centres = -1.0 + (np.arange(m, dtype=np.float64) + 0.5) * dx
     steps = int(round(t_end / dt))
     a_lat = alpha * dt / (dx * dx)
 
+    # The 2m + 1 points along a side where links meet it: every half lattice spacing from one
+    # corner to the other (the nodes' rows or columns and the points between them).
+    along = -1.0 + np.arange(2 * m + 1, dtype=np.float64) * (0.5 * dx)
+
     def walls(k: int) -> np.ndarray:
         t = (k + 1) * dt
-        lo, hi = np.full(m, -1.0), np.full(m, 2.0)
-        return np.concatenate([_bfe_wave(lo, centres, t, a, alpha, b, delta),
-                               _bfe_wave(hi, centres, t, a, alpha, b, delta),
-                               _bfe_wave(centres, lo, t, a, alpha, b, delta),
-                               _bfe_wave(centres, hi, t, a, alpha, b, delta)])
+        lo, hi = np.full(2 * m + 1, -1.0), np.full(2 * m + 1, 2.0)
+        return np.concatenate([_bfe_wave(lo, along, t, a, alpha, b, delta),
+                               _bfe_wave(hi, along, t, a, alpha, b, delta),
+                               _bfe_wave(along, lo, t, a, alpha, b, delta),
+                               _bfe_wave(along, hi, t, a, alpha, b, delta)])
 
     bc0 = walls(-1)
+    side = 2 * m + 1  # the initial per-side constants: each side's value at its first node
     return Workload(f"bfe_a{a:g}_alpha{alpha:g}_{m}", m, m, steps, A0=(a_lat, 0.0, a_lat),
-                    bc_type=(DIRICHLET,) * 4, bc_value=(float(bc0[0]), float(bc0[m]), float(bc0[2 * m]),
-                                                        float(bc0[3 * m])),
+                    bc_type=(DIRICHLET,) * 4, bc_value=(float(bc0[1]), float(bc0[side + 1]),
+                                                        float(bc0[2 * side + 1]), float(bc0[3 * side + 1])),
                     k0=1.0, k2="hbb", phi0_kind="bfe",
                     flux_c=(a / ((delta + 1.0) * c), 0.0), flux_q=delta + 1.0, src_r=b * dt, src_p=delta,
                     walls=walls,
