@@ -196,14 +196,18 @@ int btrt_step(btrt_t* h, int64_t n);
 
 /* Dirichlet values that change along the walls and in time (Eqs. (54)-(56) with phi_w(x, t),
  * as the Burgers-Fisher problem of Eqs. (67)-(69) needs) for the next `steps` >= 1 steps.
- * values[k*P + q], P = 2*(nx + ny): for the k-th step from now (k = 0 .. steps-1), the values
+ * values[k*P + q], P = 4*(nx + ny) + 4: for the k-th step from now (k = 0 .. steps-1), the values
  * phi_w of the populations that the bounce-back returns into the grid at the end of that step
- * (time t + k + 1), along side x- at rows j (q = j), x+ at rows j (q = ny + j), y- at columns i
- * (q = 2 ny + i) and y+ at columns i (q = 2 ny + nx + i); entries of periodic sides are
- * ignored. A link of node (i, j) leaving through an x side takes that side's value at row j,
- * through a y side the value at column i, and a diagonal link through a corner point the mean
- * of the two. The values are copied (host memory, read during the call); the handle allocates
- * device memory for them (P * (steps + 1) values, freed by the next call or btrt_destroy).
+ * (time t + k + 1), sampled along each side every half lattice spacing from corner to corner:
+ * x- at y = s/2 (q = s, s = 0 .. 2 ny), x+ at y = s/2 (q = 2 ny + 1 + s), y- at x = s/2
+ * (q = 4 ny + 2 + s, s = 0 .. 2 nx) and y+ at x = s/2 (q = 4 ny + 2 nx + 3 + s), in lattice
+ * units with the walls at 0 and nx (0 and ny); entries of periodic sides are ignored. Half-way
+ * bounce-back puts the wall half a spacing beyond the last node, so the link from node (i, j)
+ * along c meets it at (i + 1/2 + c_x/2, j + 1/2 + c_y/2): through an x side it takes sample
+ * 2j + 1 + c_y, through a y side sample 2i + 1 + c_x, and a diagonal link through a corner point
+ * the mean of the two sides' samples there. The values are copied (host memory, read during the
+ * call); the handle allocates device memory for them ((P + 4) * (steps + 1) values, the corner
+ * means included; freed by the next call or btrt_destroy).
  * Once set, btrt_step, btrt_solve and btrt_tune may advance at most `steps` steps past the
  * step count of this call; a new call continues from the current step. Selects the general
  * node model from the next step on. Errors: BTRT_E_INVAL for NULL values, steps < 1,

@@ -317,10 +317,11 @@ class Solver:
         return self
 
     def set_walls(self, values: np.ndarray) -> "Solver":
-        """btrt_set_walls: Dirichlet values for the next len(values) steps, each row x- (ny),
-        x+ (ny), y- (nx), y+ (nx)."""
+        """btrt_set_walls: Dirichlet values for the next len(values) steps, each row the sides
+        sampled every half lattice spacing from corner to corner: x- (2 ny + 1), x+ (2 ny + 1),
+        y- (2 nx + 1), y+ (2 nx + 1)."""
         v = np.ascontiguousarray(values, dtype=np.float64)
-        P = 2 * (self.problem.nx + self.problem.ny)
+        P = 4 * (self.problem.nx + self.problem.ny) + 4
         v = v.reshape(-1, P)
         _check(lib().btrt_set_walls(self.h, _dptr(v), int(v.shape[0])), "btrt_set_walls")
         return self

@@ -95,8 +95,9 @@ void release(btrt* h)
 
 // ---- checkpoint layout ---------------------------------------------------------------------
 // [header (kCkHeader bytes)] [f: 9 planes, storage format] [phi: one plane] [snapshot: nx*ny FP64]
-// [wall entry: 2 (nx + ny) values in the phi type, general node model only]
-constexpr char kCkMagic[8] = {'B', 'T', 'R', 'T', 'C', 'K', 'P', '1'};
+// [wall entry: one wall-table entry (Instance::wall_entry_slots() values) in the phi type,
+//  general node model only]
+constexpr char kCkMagic[8] = {'B', 'T', 'R', 'T', 'C', 'K', 'P', '2'};
 constexpr int kCkParams = 48;
 constexpr size_t kCkHeader = 512;
 
@@ -148,7 +149,7 @@ CkSizes ck_sizes(const Instance& I)
     z.f = 9 * static_cast<size_t>(I.plane) * pop_bytes(I.precision);
     z.phi = static_cast<size_t>(I.plane) * ps;
     z.snap = static_cast<size_t>(I.nx) * I.ny * 8;
-    z.wall = I.gen ? static_cast<size_t>(I.wall_entry_values()) * ps : 0;
+    z.wall = I.gen ? static_cast<size_t>(I.wall_entry_slots()) * ps : 0;
     z.total = kCkHeader + z.f + z.phi + z.snap + z.wall;
     return z;
 }
@@ -218,7 +219,7 @@ int btrt_restore(btrt_t* h, const void* buf, size_t bytes)
         return fail(BTRT_E_INVAL, "checkpoint of a %d x %d grid (precision %d) restored into a %d x %d grid (%d)",
                     hd.nx, hd.ny, hd.precision, I.nx, I.ny, I.precision);
     const size_t ps = I.precision == BTRT_F64 ? 8 : 4;
-    const size_t wall_entry = static_cast<size_t>(I.wall_entry_values()) * ps;
+    const size_t wall_entry = static_cast<size_t>(I.wall_entry_slots()) * ps;
     const size_t wall = static_cast<size_t>(hd.wall_bytes);
     if (hd.f_bytes != static_cast<int64_t>(z.f) || hd.phi_bytes != static_cast<int64_t>(z.phi) ||
         hd.snap_bytes != static_cast<int64_t>(z.snap) || (wall != 0 && wall != wall_entry) ||
@@ -376,9 +377,10 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps)
     if (steps < 1) return fail(BTRT_E_INVAL, "steps = %lld < 1", static_cast<long long>(steps));
     if (I.precision != BTRT_F64 && I.precision != BTRT_F32)
         return fail(BTRT_E_INVAL, "wall schedules need BTRT_F64 or BTRT_F32 storage");
-    const int64_t P = I.wall_entry_values();
+    const int64_t P = I.wall_entry_values(), S = I.wall_entry_slots();
     const bool wall_side[4] = {!I.perx, !I.perx, !I.pery, !I.pery};
-    const int64_t side_begin[5] = {0, I.ny, 2LL * I.ny, 2LL * I.ny + I.nx, P};
+    const int64_t sx = 2LL * I.ny + 1, sy = 2LL * I.nx + 1;
+    const int64_t side_begin[5] = {0, sx, 2 * sx, 2 * sx + sy, P};
     for (int64_t k = 0; k < steps; ++k)
         for (int q = 0; q < 4; ++q) {
             if (!wall_side[q]) continue;
@@ -388,7 +390,7 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps)
                                 static_cast<long long>(k), static_cast<long long>(e));
         }
     const size_t es = I.precision == BTRT_F64 ? 8 : 4;
-    const size_t bytes = static_cast<size_t>(P) * static_cast<size_t>(steps + 1) * es;
+    const size_t bytes = static_cast<size_t>(S) * static_cast<size_t>(steps + 1) * es;
     DeviceGuard g(h->device);
     if (g.status() != hipSuccess) return hip_fail(g.status(), "hipSetDevice");
     void* mem = nullptr;
@@ -402,12 +404,12 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps)
     hipError_t e;
     if (I.gen && I.wtab) {
         const char* cur = I.wtab + static_cast<size_t>(I.step - I.wall_t0) * I.wall_stride * es;
-        e = hipMemcpyAsync(dst, cur, static_cast<size_t>(P) * es, hipMemcpyDeviceToDevice, h->stream);
+        e = hipMemcpyAsync(dst, cur, static_cast<size_t>(S) * es, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     } else {
         e = upload_wall_entry(I, dst, h->stream);
     }
-    if (e == hipSuccess) e = upload_wall_values(I, values, static_cast<size_t>(P * steps), dst + P * es, h->stream);
+    if (e == hipSuccess) e = upload_wall_values(I, values, static_cast<size_t>(steps), dst + S * es, h->stream);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return hip_fail(e, "wall schedule upload");
@@ -418,7 +420,7 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps)
     I.wtab = dst;
     I.wall_t0 = I.step;
     I.wall_limit = I.step + steps;
-    I.wall_stride = static_cast<int>(P);
+    I.wall_stride = static_cast<int>(S);
     return ok();
 }
 

@@ -80,13 +80,19 @@ __device__ __forceinline__ T source_at(const SweepArgs<T>& a, int n, int x, int 
 template <typename T_>
 struct Plain {
     using T = T_;
-    // With a wall table (general model) an edge node takes its Dirichlet values from the table
-    // entry of the launch's first step.
+    // With a wall table (TABLE: the general node model) an edge node takes its Dirichlet values
+    // from the table entry of the launch's first step.
+    template <bool TABLE>
     __device__ __forceinline__ static void pull(const SweepArgs<T>& a, int x, int y, T f[9])
     {
-        T w[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
-        if (a.wtab != nullptr && (x == 0 || y == 0 || x == a.nx - 1 || y == a.ny - 1)) table_walls(a, x, y, 0, w);
-        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery, w, f);
+        gather(a.fin, a.plane, x, y, a.nx, a.ny, a.pitch, a.perx, a.pery,
+               [&](int i, bool ox, bool oy) {
+                   if constexpr (TABLE)
+                       return table_wall(a, x, y, 0, i, ox, oy);
+                   else
+                       return side_wall(a.wall, i, ox, oy);
+               },
+               f);
     }
     __device__ __forceinline__ static void settle(const SweepArgs<T>&, T*, T) {}
     // Raw loads of one node's pull (see walk_load): value read for each direction.
@@ -138,13 +144,15 @@ struct Dev {
     {
         return C::enc((f - feq_dir(i, phi, a.ax, a.ay, a.bx, a.by)) * a.dev_scale);
     }
+    template <bool TABLE>  // the 16-bit formats take per-side constants only
     __device__ __forceinline__ static void pull(const SweepArgs<float>& a, int x, int y, float f[9])
     {
         const unsigned short* __restrict__ H = reinterpret_cast<const unsigned short*>(a.fin);
         const float* __restrict__ P = a.phi_prev;
         const int64_t p = a.plane;
         gather_with<float>([&](int i, int idx) { return rebuild(a, i, P[idx], H[i * p + idx]); }, x, y, a.nx, a.ny,
-                           a.pitch, a.perx, a.pery, a.wall, f);
+                           a.pitch, a.perx, a.pery,
+                           [&](int i, bool ox, bool oy) { return side_wall(a.wall, i, ox, oy); }, f);
     }
     // Raw loads of one node's pull: the 16-bit code and phi(t-1) of the node it comes from.
     struct Raw {
@@ -195,7 +203,7 @@ __device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx,
     const int y = ty * rows + static_cast<int>(threadIdx.x / kTileX);
     if (x >= a.nx || y >= a.ny) return;
     T f[9];
-    F::pull(a, x, y, f);
+    F::template pull<(KM & kGen) != 0>(a, x, y, f);
     const int n = y * a.pitch + x;
     const T phi = collide<T, SRC, KM>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y, 0), n);
     F::put(a, n, f, phi);
@@ -267,7 +275,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         gxs[j] = gx;
         gys[j] = gy;
         if (e) {
-            F::pull(a, gx, gy, f[j]);
+            F::template pull<(KM & kGen) != 0>(a, gx, gy, f[j]);
             pp[j] = a.phi_prev[gy * a.pitch + gx];
         }
     }
@@ -296,20 +304,22 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         const int l = (iy + 1) * EX + ix + 1;
         const bool okxm = a.perx || gx > 0, okxp = a.perx || gx < nx - 1;
         const bool okym = a.pery || gy > 0, okyp = a.pery || gy < ny - 1;
-        T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
-        if constexpr ((KM & kGen) != 0) {
-            if (!(okxm && okxp && okym && okyp)) table_walls(a, gx, gy, 1, wv);
-        }
+        auto wv = [&](int i, bool ox, bool oy) {
+            if constexpr ((KM & kGen) != 0)
+                return table_wall(a, gx, gy, 1, i, ox, oy);
+            else
+                return side_wall(a.wall, i, ox, oy);
+        };
         T g[9];
         g[0] = lf[0][l];
-        g[1] = okxm ? lf[1][l - 1] : bounce(lf[3][l], tw1, wv[0]);
-        g[2] = okym ? lf[2][l - EX] : bounce(lf[4][l], tw1, wv[2]);
-        g[3] = okxp ? lf[3][l + 1] : bounce(lf[1][l], tw1, wv[1]);
-        g[4] = okyp ? lf[4][l + EX] : bounce(lf[2][l], tw1, wv[3]);
-        g[5] = (okxm && okym) ? lf[5][l - EX - 1] : bounce(lf[7][l], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
-        g[6] = (okxp && okym) ? lf[6][l - EX + 1] : bounce(lf[8][l], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
-        g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
-        g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
+        g[1] = okxm ? lf[1][l - 1] : bounce(lf[3][l], tw1, wv(1, true, false));
+        g[2] = okym ? lf[2][l - EX] : bounce(lf[4][l], tw1, wv(2, false, true));
+        g[3] = okxp ? lf[3][l + 1] : bounce(lf[1][l], tw1, wv(3, true, false));
+        g[4] = okyp ? lf[4][l + EX] : bounce(lf[2][l], tw1, wv(4, false, true));
+        g[5] = (okxm && okym) ? lf[5][l - EX - 1] : bounce(lf[7][l], tw5, wv(5, !okxm, !okym));
+        g[6] = (okxp && okym) ? lf[6][l - EX + 1] : bounce(lf[8][l], tw5, wv(6, !okxp, !okym));
+        g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wv(7, !okxp, !okyp));
+        g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wv(8, !okxm, !okyp));
         const int n = gy * a.pitch + gx;
         const T phi = collide<T, SRC, KM>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy, 1), n);
         F::put(a, n, g, phi);
@@ -434,19 +444,21 @@ __device__ __forceinline__ T walk_collide(const SweepArgs<T>& a, const T up[3], 
     }
     const bool okym = WALLS ? row.okm : true, okyp = WALLS ? row.okp : true;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
-    T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
-    if constexpr (WALLS && (KM & kGen) != 0) {
-        if (!(okxm && okxp && okym && okyp)) table_walls(a, x, row.y, lvl, wv);
-    }
+    auto wv = [&](int i, bool ox, bool oy) {
+        if constexpr (WALLS && (KM & kGen) != 0)
+            return table_wall(a, x, row.y, lvl, i, ox, oy);
+        else
+            return side_wall(a.wall, i, ox, oy);
+    };
     g[0] = m[0];
-    g[1] = okxm ? s1 : bounce(m[3], tw1, wv[0]);
-    g[2] = okym ? up[0] : bounce(m[4], tw1, wv[2]);
-    g[3] = okxp ? s3 : bounce(m[1], tw1, wv[1]);
-    g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, wv[3]);
-    g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
-    g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
-    g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
-    g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
+    g[1] = okxm ? s1 : bounce(m[3], tw1, wv(1, true, false));
+    g[2] = okym ? up[0] : bounce(m[4], tw1, wv(2, false, true));
+    g[3] = okxp ? s3 : bounce(m[1], tw1, wv(3, true, false));
+    g[4] = okyp ? fresh.f[4] : bounce(m[2], tw1, wv(4, false, true));
+    g[5] = (okxm && okym) ? s5 : bounce(m[7], tw5, wv(5, !okxm, !okym));
+    g[6] = (okxp && okym) ? s6 : bounce(m[8], tw5, wv(6, !okxp, !okym));
+    g[7] = (okxp && okyp) ? s7 : bounce(m[5], tw5, wv(7, !okxp, !okyp));
+    g[8] = (okxm && okyp) ? s8 : bounce(m[6], tw5, wv(8, !okxm, !okyp));
     const int n = row.y * a.pitch + x;
     return collide<T, SRC, KM>(a, g, mid.phi, source_at<T, SRC>(a, n, x, row.y, lvl), n);
 }
@@ -459,7 +471,8 @@ template <typename F>
 struct WalkIn {
     typename F::Raw raw;
     typename F::T phi;   // phi(t-1) of the node
-    typename F::T w[4];  // general model: the node's Dirichlet values from the wall table
+    typename F::T w[9];  // general model: the Dirichlet value of each pull that crosses a wall
+    //                        (directions 1..8, from the wall table; 0 where the pull is a node)
     int ok;              // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
 };
 
@@ -489,7 +502,18 @@ __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int
                         ok5 ? rm + xm : n, ok6 ? rm + xp : n, ok7 ? rp + xp : n, ok8 ? rp + xm : n};
     F::fetch(a, plane, idx, in.raw);
     in.phi = a.phi_prev[n];
-    if constexpr (WALLS && GEN) table_walls(a, x, y, 0, in.w);  // x, y are in the grid
+    if constexpr (WALLS && GEN) {  // x, y are in the grid, so every table index is in range
+        using T = typename F::T;
+        const bool oxm = !okxm, oxp = !okxp, oym = !okym, oyp = !okyp;
+        in.w[1] = oxm ? table_wall(a, x, y, 0, 1, true, false) : T(0);
+        in.w[2] = oym ? table_wall(a, x, y, 0, 2, false, true) : T(0);
+        in.w[3] = oxp ? table_wall(a, x, y, 0, 3, true, false) : T(0);
+        in.w[4] = oyp ? table_wall(a, x, y, 0, 4, false, true) : T(0);
+        in.w[5] = (oxm || oym) ? table_wall(a, x, y, 0, 5, oxm, oym) : T(0);
+        in.w[6] = (oxp || oym) ? table_wall(a, x, y, 0, 6, oxp, oym) : T(0);
+        in.w[7] = (oxp || oyp) ? table_wall(a, x, y, 0, 7, oxp, oyp) : T(0);
+        in.w[8] = (oxm || oyp) ? table_wall(a, x, y, 0, 8, oxm, oyp) : T(0);
+    }
     in.ok = (okxm ? 1 : 0) | (okxp ? 2 : 0) | (okym ? 4 : 0) | (okyp ? 8 : 0) | ((colok && w.ok) ? 16 : 0);
 }
 
@@ -513,20 +537,21 @@ __device__ __forceinline__ void walk_finish(const SweepArgs<typename F::T>& a, c
     T v[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) v[i] = F::value(a, in.raw, i, opp[i], !ok[i]);
-    T wv[4] = {a.wall[0], a.wall[1], a.wall[2], a.wall[3]};
-    if constexpr (GEN) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) wv[q] = in.w[q];
-    }
+    auto wv = [&](int i, bool ox, bool oy) {
+        if constexpr (GEN)
+            return in.w[i];
+        else
+            return side_wall(a.wall, i, ox, oy);
+    };
     f[0] = v[0];
-    f[1] = ok[1] ? v[1] : bounce(v[1], tw1, wv[0]);
-    f[2] = ok[2] ? v[2] : bounce(v[2], tw1, wv[2]);
-    f[3] = ok[3] ? v[3] : bounce(v[3], tw1, wv[1]);
-    f[4] = ok[4] ? v[4] : bounce(v[4], tw1, wv[3]);
-    f[5] = ok[5] ? v[5] : bounce(v[5], tw5, wall_value(!okxm, !okym, wv[0], wv[2]));
-    f[6] = ok[6] ? v[6] : bounce(v[6], tw5, wall_value(!okxp, !okym, wv[1], wv[2]));
-    f[7] = ok[7] ? v[7] : bounce(v[7], tw5, wall_value(!okxp, !okyp, wv[1], wv[3]));
-    f[8] = ok[8] ? v[8] : bounce(v[8], tw5, wall_value(!okxm, !okyp, wv[0], wv[3]));
+    f[1] = ok[1] ? v[1] : bounce(v[1], tw1, wv(1, true, false));
+    f[2] = ok[2] ? v[2] : bounce(v[2], tw1, wv(2, false, true));
+    f[3] = ok[3] ? v[3] : bounce(v[3], tw1, wv(3, true, false));
+    f[4] = ok[4] ? v[4] : bounce(v[4], tw1, wv(4, false, true));
+    f[5] = ok[5] ? v[5] : bounce(v[5], tw5, wv(5, !okxm, !okym));
+    f[6] = ok[6] ? v[6] : bounce(v[6], tw5, wv(6, !okxp, !okym));
+    f[7] = ok[7] ? v[7] : bounce(v[7], tw5, wv(7, !okxp, !okyp));
+    f[8] = ok[8] ? v[8] : bounce(v[8], tw5, wv(8, !okxm, !okyp));
     phi_prev = in.phi;
     if (!node) {
 #pragma unroll

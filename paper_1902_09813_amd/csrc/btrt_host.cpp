@@ -90,7 +90,7 @@ Layout layout_for(int nx, int ny, int precision, int src_kind, bool afield)
         L.src_y = take(static_cast<size_t>(ny) * ps);
     }
     L.afield = afield ? take(3 * plane * ps) : 0;
-    L.wall0 = take(2 * (static_cast<size_t>(nx) + static_cast<size_t>(ny)) * ps);
+    L.wall0 = take((4 * (static_cast<size_t>(nx) + static_cast<size_t>(ny)) + 8) * ps);  // one wall-table entry
     L.total = off;
     return L;
 }
@@ -469,35 +469,59 @@ SweepArgs<T> sweep_args(const Instance& I, int parity)
 
 std::vector<double> wall_entry_constants(const Instance& I)
 {
+    const size_t sx = 2 * static_cast<size_t>(I.ny) + 1, sy = 2 * static_cast<size_t>(I.nx) + 1;
     std::vector<double> v(static_cast<size_t>(I.wall_entry_values()));
-    for (int j = 0; j < I.ny; ++j) {
-        v[j] = I.wall[0];
-        v[I.ny + j] = I.wall[1];
-    }
-    for (int i = 0; i < I.nx; ++i) {
-        v[2 * I.ny + i] = I.wall[2];
-        v[2 * I.ny + I.nx + i] = I.wall[3];
-    }
+    std::fill(v.begin(), v.begin() + sx, I.wall[0]);
+    std::fill(v.begin() + sx, v.begin() + 2 * sx, I.wall[1]);
+    std::fill(v.begin() + 2 * sx, v.begin() + 2 * sx + sy, I.wall[2]);
+    std::fill(v.begin() + 2 * sx + sy, v.end(), I.wall[3]);
     return v;
 }
 
-hipError_t upload_wall_values(const Instance& I, const double* v, size_t count, char* dst, hipStream_t s)
+namespace {
+template <typename T>
+std::vector<T> wall_entries(const Instance& I, const double* v, size_t rows)
+{
+    const size_t P = static_cast<size_t>(I.wall_entry_values()), S = static_cast<size_t>(I.wall_entry_slots());
+    const size_t sx = 2 * static_cast<size_t>(I.ny) + 1, sy = 2 * static_cast<size_t>(I.nx) + 1;
+    std::vector<T> out(rows * S);
+    for (size_t k = 0; k < rows; ++k) {
+        const double* r = v + k * P;
+        T* o = out.data() + k * S;
+        for (size_t q = 0; q < P; ++q) o[q] = static_cast<T>(r[q]);
+        // Corner samples: x- and x+ at their first (y = 0) and last (y = ny) sample, y- and y+
+        // likewise at x = 0 and x = nx. A link through a corner takes the mean of the two sides
+        // that meet there, computed in the storage type as the kernels do for constant sides.
+        const T xm0 = o[0], xm1 = o[sx - 1], xp0 = o[sx], xp1 = o[2 * sx - 1];
+        const T ym0 = o[2 * sx], ym1 = o[2 * sx + sy - 1], yp0 = o[2 * sx + sy], yp1 = o[2 * sx + 2 * sy - 1];
+        o[P + 0] = T(0.5) * (xm0 + ym0);
+        o[P + 1] = T(0.5) * (xp0 + ym1);
+        o[P + 2] = T(0.5) * (xp1 + yp1);
+        o[P + 3] = T(0.5) * (xm1 + yp0);
+    }
+    return out;
+}
+}  // namespace
+
+hipError_t upload_wall_values(const Instance& I, const double* v, size_t rows, char* dst, hipStream_t s)
 {
     hipError_t e;
-    std::vector<float> f;
     if (I.precision == BTRT_F64) {
-        e = hipMemcpyAsync(dst, v, count * sizeof(double), hipMemcpyHostToDevice, s);
+        const std::vector<double> d = wall_entries<double>(I, v, rows);
+        e = hipMemcpyAsync(dst, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host buffer is a local
     } else {
-        f.assign(v, v + count);
-        e = hipMemcpyAsync(dst, f.data(), count * sizeof(float), hipMemcpyHostToDevice, s);
+        const std::vector<float> f = wall_entries<float>(I, v, rows);
+        e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    return e == hipSuccess ? hipStreamSynchronize(s) : e;  // the host buffers are locals
+    return e;
 }
 
 hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s)
 {
     const std::vector<double> v = wall_entry_constants(I);
-    return upload_wall_values(I, v.data(), v.size(), dst, s);
+    return upload_wall_values(I, v.data(), 1, dst, s);
 }
 
 template <typename T>

@@ -72,9 +72,10 @@ struct Instance {
     bool k0_one = false;  // k0 = 1 exactly: kernels without the (1 - k0) f_i term
     bool afield = false;  // per-node A0(x) planes in the workspace
     double growth = 0.0;  // source growth rate per step (Scheme 2 correction when nonzero)
-    // General node model (kGen): wall table entries of 2 (nx + ny) values in the phi type; the
-    // pull at step count t reads entry (t - wall_t0) at wtab + (t - wall_t0) * wall_stride. Steps
-    // may advance the count up to wall_limit.
+    // General node model (kGen): wall table entries of wall_entry_slots() values in the phi type
+    // (the wall_entry_values() samples a caller gives per step, see btrt_set_walls, then the four
+    // corner means); the pull at step count t reads entry (t - wall_t0) at
+    // wtab + (t - wall_t0) * wall_stride. Steps may advance the count up to wall_limit.
     bool gen = false;
     const char* wtab = nullptr;
     int64_t wall_t0 = 0;
@@ -97,7 +98,10 @@ struct Instance {
         if (gen) return k1 | btrtk::kGen;
         return k0_one ? (k1 | btrtk::kK0One) : k1;
     }
-    int wall_entry_values() const { return 2 * (nx + ny); }
+    // Samples per step of a wall schedule: each side every half spacing, corners included.
+    int wall_entry_values() const { return 4 * (nx + ny) + 4; }
+    // Device slots per wall-table entry: the samples and the means at the four corners.
+    int wall_entry_slots() const { return wall_entry_values() + 4; }
 };
 
 // Places a validated problem into mem (at least layout_for(...).total bytes, 256-byte
@@ -107,10 +111,13 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
                    const btrt_source_t* R, const btrt_bc_t* bc, const Resolved& r, const double* phi0, char* mem,
                    hipStream_t s);
 
-// Wall-table entry of the per-side constants (2 (nx + ny) values, see Instance).
+// Wall samples of the per-side constants (one step of a schedule, wall_entry_values() values).
 std::vector<double> wall_entry_constants(const Instance& I);
-// Copies count FP64 wall values to device memory dst in I's phi type; synchronises s.
-hipError_t upload_wall_values(const Instance& I, const double* v, size_t count, char* dst, hipStream_t s);
+// Writes `rows` wall-table entries to device memory dst in I's phi type from rows of FP64
+// samples (wall_entry_values() each): the samples, then the mean of the two sides' samples at
+// each corner (x-y-, x+y-, x+y+, x-y+), rounded as the kernels round the mean of two per-side
+// constants. Synchronises s.
+hipError_t upload_wall_values(const Instance& I, const double* v, size_t rows, char* dst, hipStream_t s);
 hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s);
 
 // Sweep arguments with the buffer pointers for the given parity (0: f[0] -> f[1]).

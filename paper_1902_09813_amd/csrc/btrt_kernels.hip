@@ -44,6 +44,17 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(const double* __restric
     out[y * pitch + x] = static_cast<T>(in[k]);
 }
 
+// The pull of a sweep's first step, for a handle with or without a wall table (the gathers
+// serve every node model).
+template <typename F>
+__device__ __forceinline__ void pull_any(const SweepArgs<typename F::T>& a, int x, int y, typename F::T f[9])
+{
+    if (a.wtab != nullptr)
+        F::template pull<true>(a, x, y, f);
+    else
+        F::template pull<false>(a, x, y, f);
+}
+
 // phi(t) (or one population f_i(t)) at every node into a dense FP64 array.
 template <typename F>
 __global__ __launch_bounds__(kBlock) void gather_field_kernel(GatherArgs<typename F::T> a)
@@ -54,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void gather_field_kernel(GatherArgs<typenam
     const int y = static_cast<int>(k / a.s.nx);
     const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.s.nx);
     T f[9];
-    F::pull(a.s, x, y, f);
+    pull_any<F>(a.s, x, y, f);
     T v = T(0);
     if (a.population < 0) {
         v = sum9(f);
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(GatherArgs<typename F::T
         const int y = static_cast<int>(k / a.s.nx);
         const int x = static_cast<int>(k - static_cast<int64_t>(y) * a.s.nx);
         T f[9];
-        F::pull(a.s, x, y, f);
+        pull_any<F>(a.s, x, y, f);
         const double phi = static_cast<double>(sum9(f));
         if (!isfinite(phi)) v[5] += 1.0;
         if constexpr (MODE == kResidual) {

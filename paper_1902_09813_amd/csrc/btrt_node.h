@@ -70,23 +70,46 @@ __host__ __device__ inline T wall_value(bool out_x, bool out_y, T vx, T vy)
     return (out_x && out_y) ? T(0.5) * (vx + vy) : (out_x ? vx : vy);
 }
 
-// Dirichlet values of node (x, y) at step lvl of a launch from the wall table: side x- and x+
-// at the node's row, y- and y+ at its column.
+// Velocity components of direction i (the order of Eq. (85)); i is a constant wherever these
+// are used, so they fold away.
+__host__ __device__ constexpr int dir_cx(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
+__host__ __device__ constexpr int dir_cy(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
+
+// Dirichlet value phi_w for the pull of direction i at a node whose pull crosses a wall, from
+// the per-side constants w = (x-, x+, y-, y+): the population bounced back left the node along
+// -c_i, through side x- when c_ix > 0 (x+ when < 0) and y- when c_iy > 0 (y+ when < 0).
 template <typename T>
-__host__ __device__ inline void table_walls(const SweepArgs<T>& a, int x, int y, int lvl, T w[4])
+__host__ __device__ inline T side_wall(const T w[4], int i, bool out_x, bool out_y)
+{
+    return wall_value(out_x, out_y, w[dir_cx(i) > 0 ? 0 : 1], w[dir_cy(i) > 0 ? 2 : 3]);
+}
+
+// The same from the wall table entry of step lvl of a launch (general node model). Half-way
+// bounce-back (Eqs. (54)-(56)) puts a wall half a spacing beyond the last node, so the link from
+// node (x, y) (at x + 1/2, y + 1/2) along -c_i meets it at x + 1/2 - c_ix/2, y + 1/2 - c_iy/2.
+// An entry holds each side sampled every half spacing from corner to corner: x- (2 ny + 1
+// samples), x+ (2 ny + 1), y- (2 nx + 1), y+ (2 nx + 1), sample s at position s/2; the link then
+// reads sample 2y + 1 - c_iy of its x side or 2x + 1 - c_ix of its y side. Four more slots hold,
+// for the links that meet a corner point, the mean of the two sides' corner samples (corners
+// x-y-, x+y-, x+y+, x-y+; filled by the library). Every index lies inside its side for a node
+// of the grid.
+template <typename T>
+__host__ __device__ inline T table_wall(const SweepArgs<T>& a, int x, int y, int lvl, int i, bool out_x, bool out_y)
 {
     const T* e = a.wtab + lvl * a.wstride;
-    w[0] = e[y];
-    w[1] = e[a.ny + y];
-    w[2] = e[2 * a.ny + x];
-    w[3] = e[2 * a.ny + a.nx + x];
+    const int cx = dir_cx(i), cy = dir_cy(i);
+    const int sx = 2 * a.ny + 1, sy = 2 * a.nx + 1;
+    if (out_x && out_y) return e[2 * sx + 2 * sy + (cy > 0 ? (cx > 0 ? 0 : 1) : (cx > 0 ? 3 : 2))];
+    if (out_x) return e[(cx > 0 ? 0 : sx) + 2 * y + 1 - cy];
+    return e[2 * sx + (cy > 0 ? 0 : sy) + 2 * x + 1 - cx];
 }
 
 // Pull f_i(x, t) for all nine directions: load(i, idx) returns the post-collision value
-// f_i+(t-1) stored at in-plane index idx (for a storage format of the caller's choice).
-template <typename T, typename Load>
+// f_i+(t-1) stored at in-plane index idx (for a storage format of the caller's choice);
+// wall(i, out_x, out_y) the Dirichlet value of a pull that crosses a wall (side_wall, table_wall).
+template <typename T, typename Load, typename Wall>
 __host__ __device__ inline void gather_with(Load load, int x, int y, int nx, int ny, int pitch, int perx, int pery,
-                                            const T* wall, T f[9])
+                                            Wall wall, T f[9])
 {
     const int n = y * pitch + x;
     if (x > 0 && x < nx - 1 && y > 0 && y < ny - 1) {
@@ -111,20 +134,20 @@ __host__ __device__ inline void gather_with(Load load, int x, int y, int nx, int
     const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
     const T tw1 = T(2) * Lat<T>::w1, tw5 = T(2) * Lat<T>::w5;
     f[0] = load(0, n);
-    f[1] = okxm ? load(1, r0 + xm) : bounce(load(3, n), tw1, wall[0]);
-    f[2] = okym ? load(2, rm + x) : bounce(load(4, n), tw1, wall[2]);
-    f[3] = okxp ? load(3, r0 + xp) : bounce(load(1, n), tw1, wall[1]);
-    f[4] = okyp ? load(4, rp + x) : bounce(load(2, n), tw1, wall[3]);
-    f[5] = (okxm && okym) ? load(5, rm + xm) : bounce(load(7, n), tw5, wall_value(!okxm, !okym, wall[0], wall[2]));
-    f[6] = (okxp && okym) ? load(6, rm + xp) : bounce(load(8, n), tw5, wall_value(!okxp, !okym, wall[1], wall[2]));
-    f[7] = (okxp && okyp) ? load(7, rp + xp) : bounce(load(5, n), tw5, wall_value(!okxp, !okyp, wall[1], wall[3]));
-    f[8] = (okxm && okyp) ? load(8, rp + xm) : bounce(load(6, n), tw5, wall_value(!okxm, !okyp, wall[0], wall[3]));
+    f[1] = okxm ? load(1, r0 + xm) : bounce(load(3, n), tw1, wall(1, true, false));
+    f[2] = okym ? load(2, rm + x) : bounce(load(4, n), tw1, wall(2, false, true));
+    f[3] = okxp ? load(3, r0 + xp) : bounce(load(1, n), tw1, wall(3, true, false));
+    f[4] = okyp ? load(4, rp + x) : bounce(load(2, n), tw1, wall(4, false, true));
+    f[5] = (okxm && okym) ? load(5, rm + xm) : bounce(load(7, n), tw5, wall(5, !okxm, !okym));
+    f[6] = (okxp && okym) ? load(6, rm + xp) : bounce(load(8, n), tw5, wall(6, !okxp, !okym));
+    f[7] = (okxp && okyp) ? load(7, rp + xp) : bounce(load(5, n), tw5, wall(7, !okxp, !okyp));
+    f[8] = (okxm && okyp) ? load(8, rp + xm) : bounce(load(6, n), tw5, wall(8, !okxm, !okyp));
 }
 
 // Pull from nine planes of T (plane stride `plane`).
-template <typename T>
+template <typename T, typename Wall>
 __host__ __device__ inline void gather(const T* __restrict__ fin, int64_t plane, int x, int y, int nx,
-                                       int ny, int pitch, int perx, int pery, const T* wall, T f[9])
+                                       int ny, int pitch, int perx, int pery, Wall wall, T f[9])
 {
     gather_with<T>([fin, plane](int i, int idx) { return fin[i * plane + idx]; }, x, y, nx, ny, pitch, perx, pery,
                    wall, f);

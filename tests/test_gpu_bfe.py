@@ -9,7 +9,10 @@ walls and in time (btrt_set_walls).
 * a schedule holding the per-side constants reproduces a handle without one, bit for bit;
 * a schedule set in two parts equals one set at once; steps past its end are refused and leave
   the state untouched; btrt_tune stays inside it;
-* FP32 storage within a stated bound of the oracle; Tables 4 and 5 from the HIP path's field;
+* FP32 storage within a stated bound of the oracle; Tables 4 and 5 from the HIP path's field, to
+  the printed digits (the walls taken where each link meets them);
+* unequal walls that vary along every side, with a different value at each corner from each of
+  the two sides (the corner links take their mean), in every launch shape;
 * batches and the server refuse the general model.
 """
 import sys
@@ -101,7 +104,8 @@ def test_constant_schedule_equals_constant_walls(precision):
     nx, ny, steps = 70, 45, 29
     w = W.Workload("walls_const", nx, ny, steps, A0=(0.03, 0.004, 0.02), flux_a=(0.04, -0.03), flux_b=(0.02, 0.0),
                    bc_type=(1, 1, 1, 1), bc_value=(0.2, -0.1, 0.5, 0.3), seed=11)
-    row = np.concatenate([np.full(ny, 0.2), np.full(ny, -0.1), np.full(nx, 0.5), np.full(nx, 0.3)])
+    row = np.concatenate([np.full(2 * ny + 1, 0.2), np.full(2 * ny + 1, -0.1), np.full(2 * nx + 1, 0.5),
+                          np.full(2 * nx + 1, 0.3)])
     for shape in [(1, 4, 0, 0), (2, 0, 0, 1), (4, 8, 1, 0), (3, 16, 4, 0)]:
         with btrt.Solver(btrt.problem_from_workload(w, precision=precision), w.phi0()) as a:
             a.set_launch(*shape).step(steps)
@@ -134,9 +138,9 @@ def test_schedule_in_parts_and_its_end():
         _, used = s.tune(1000)
         assert used <= 20 and s.info().step == n1 + n2 + used
         with pytest.raises(btrt.BtrtError):
-            s.set_walls(np.full((3, 2 * (w.nx + w.ny)), np.nan))
+            s.set_walls(np.full((3, 4 * (w.nx + w.ny) + 4), np.nan))
         with pytest.raises(btrt.BtrtError):
-            s.set_walls(np.zeros((0, 2 * (w.nx + w.ny))))
+            s.set_walls(np.zeros((0, 4 * (w.nx + w.ny) + 4)))
 
 
 def test_fp32_bound():
@@ -162,7 +166,33 @@ def test_tables_4_5_from_the_gpu(a, alpha, printed):
     gre = O.gre(phi, exact(w, w.steps))
     say(f"    GRE {gre:.4e} printed {printed:.4e}")
     assert err[0] == pytest.approx(gre, rel=1e-12)
-    assert gre == pytest.approx(printed, rel=0.08)
+    assert gre == pytest.approx(printed, rel=2e-4)
+
+
+def rough_walls(w, seed=21):
+    """A schedule of walls that differ along each side, between the sides and from step to step,
+    so that every link of the boundary carries its own value; the two sides meeting at a corner
+    disagree there."""
+    rng = np.random.default_rng(seed)
+    base = rng.uniform(-0.5, 1.0, 4 * (w.nx + w.ny) + 4)
+    return lambda k: base * (1.0 + 0.01 * np.sin(0.3 * k)) + 0.02 * k / max(w.steps, 1)
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1, 1), (0, 0, 1, 1), (1, 1, 0, 0)], ids=["walls", "x_periodic", "y_periodic"])
+def test_rough_walls_every_link_and_corner(bc):
+    w = W.Workload("rough_walls", 71, 45, 33, A0=(0.03, 0.006, 0.02), flux_a=(0.03, -0.02), flux_b=(0.02, 0.01),
+                   beta=0.5, bc_type=bc, bc_value=tuple(0.1 * (q + 1) if t else 0.0 for q, t in enumerate(bc)),
+                   k0=0.9, k2=(1.1, 0.95, 0.95, 1.2), seed=17)
+    w.walls = rough_walls(w)
+    say(f"[gpu] rough walls {w.nx}x{w.ny} bc={bc} steps={w.steps}")
+    o = run_oracle(w)
+    for shape in [(1, 4, 0, 0), (2, 0, 0, 1), (3, 16, 4, 0), (4, 8, 1, 0), (7, 64, 1, 0)]:
+        with solver(w) as s:
+            s.set_launch(*shape).step(w.steps)
+            phi, f = s.field(), s.populations()
+        e_phi, e_f = normwise(phi, o.phi()), normwise(f, o.f)
+        say(f"    shape {shape}: normwise phi {e_phi:.3e}  f {e_f:.3e}")
+        assert e_phi <= 1e-12 and e_f <= 1e-12, shape
 
 
 def test_batch_and_server_refuse_the_general_model():
@@ -178,5 +208,5 @@ def test_batch_and_server_refuse_the_general_model():
     q = btrt.problem_from_workload(W.c1(), precision=btrt.F16DEV)
     with btrt.Solver(q, W.c1().phi0()) as s:
         with pytest.raises(btrt.BtrtError) as e:
-            s.set_walls(np.zeros((2, 4 * 64)))
+            s.set_walls(np.zeros((2, 4 * 128 + 4)))
         assert e.value.code == btrt.E_INVAL

@@ -65,7 +65,7 @@ def test_resume_under_a_wall_schedule():
     # Into a handle of the plain problem (no general model): it switches to the wall table.
     wc = W.Workload("walls_table", 40, 30, 0, A0=(0.03, 0.0, 0.02), flux_a=(0.02, 0.01), bc_type=(1, 1, 1, 1),
                     bc_value=(0.1, 0.2, 0.3, 0.4), seed=3)
-    rows = np.random.default_rng(1).uniform(0.0, 1.0, (30, 2 * (40 + 30)))
+    rows = np.random.default_rng(1).uniform(0.0, 1.0, (30, 4 * (40 + 30) + 4))
     with btrt.Solver(btrt.problem_from_workload(wc), wc.phi0()) as ref:
         ref.set_walls(rows).step(30)
         want = ref.populations()
