@@ -277,6 +277,29 @@ int btrt_error(btrt_t* h, const double* ref, double out[3]);
  * steps have been taken. Reports the steps taken and the last residual. Synchronises. */
 int btrt_solve(btrt_t* h, double tol, int64_t max_steps, int64_t* steps_taken, double* residual);
 
+/* Bytes of the fixed device array btrt_solve_static works in (16 MiB): a 256 x 256 grid fits in
+ * any storage format, larger ones in the narrower formats (btrt_workspace_size() gives the need). */
+#define BTRT_STATIC_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): btrt_create + btrt_solve + btrt_field + btrt_destroy in one call, allocating
+ * nothing. Every device buffer of the solve (the populations, phi planes, the Eq. (64) snapshot,
+ * staging and reduction partials: a handle's workspace) lives in a fixed array of
+ * BTRT_STATIC_BYTES bytes that the library holds on each device it runs on until the process
+ * ends. Arguments are those of btrt_create (grid->workspace must be NULL; grid->stream NULL runs
+ * on the device's null stream, none is created), then those of btrt_solve: tol and max_steps,
+ * the steps taken and the last Eq. (64) residual (either may be NULL). phi_out receives phi at
+ * the end (nx*ny, caller-owned host memory), also after BTRT_E_UNSTABLE. The results are those
+ * of btrt_create, btrt_solve and btrt_field on the same arguments with the automatic launch
+ * shape, bit for bit. Calls on one device share the array: within a process they run one at a
+ * time (a lock per device); each call starts from its own inputs and leaves nothing running on
+ * the array when it returns. Errors: those of btrt_create and btrt_solve; BTRT_E_INVAL also for a
+ * workspace, a NULL phi_out, or a grid whose workspace would exceed BTRT_STATIC_BYTES (use
+ * btrt_create). Synchronises. */
+int btrt_solve_static(const btrt_grid_t* grid, const btrt_flux_t* B, const btrt_diff_t* K, const btrt_dterm_t* D,
+                      const btrt_source_t* R, const btrt_bc_t* bc, const btrt_relax_t* relax, const double* phi0,
+                      double tol, int64_t max_steps, double* phi_out, int64_t* steps_taken, double* residual);
+
 /* Waits for all work enqueued on the handle's stream. */
 int btrt_sync(btrt_t* h);
 

@@ -34,7 +34,8 @@ EXPORTS = ("btrt_validate", "btrt_workspace_size", "btrt_create", "btrt_step", "
            "btrt_batch_set_config", "btrt_batch_get_config", "btrt_batch_tune", "btrt_batch_steps",
            "btrt_batch_sync", "btrt_batch_destroy",
            "btrt_server_create", "btrt_server_submit", "btrt_server_pump", "btrt_server_info",
-           "btrt_server_result", "btrt_server_stats", "btrt_server_clock", "btrt_server_destroy")
+           "btrt_server_result", "btrt_server_stats", "btrt_server_clock", "btrt_server_destroy",
+           "btrt_solve_static")
 
 
 class Grid(ctypes.Structure):
@@ -192,6 +193,8 @@ def lib() -> ctypes.CDLL:
             "btrt_server_stats": ([hp, P(ServerStats)], ctypes.c_int),
             "btrt_server_clock": ([hp], ctypes.c_double),
             "btrt_server_destroy": ([hp], ctypes.c_int),
+            "btrt_solve_static": ([P(Grid), P(Flux), P(Diff), P(DTerm), P(Source), P(BC), P(Relax), dp, ctypes.c_double,
+                                   ctypes.c_int64, dp, P(ctypes.c_int64), dp], ctypes.c_int),
             "btrt_strerror": ([ctypes.c_int], ctypes.c_char_p),
             "btrt_last_error": ([], ctypes.c_char_p),
         }
@@ -417,6 +420,24 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+STATIC_BYTES = 16 << 20  # BTRT_STATIC_BYTES
+
+
+def solve_static(problem: Problem, phi0: np.ndarray, tol: float, max_steps: int, stream: Optional[int] = None):
+    """btrt_solve_static: create, solve and read phi in one call that allocates no device memory
+    (the library's fixed array holds every buffer). Returns (phi, steps taken, last residual)."""
+    phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(problem.ny, problem.nx)
+    g = problem.grid
+    grid = Grid(g.nx, g.ny, g.precision, g.device, stream, None, 0)
+    out = np.empty((problem.ny, problem.nx), dtype=np.float64)
+    steps = ctypes.c_int64()
+    res = ctypes.c_double()
+    b = ctypes.byref
+    _check(lib().btrt_solve_static(b(grid), *problem.args()[1:], _dptr(phi0), float(tol), int(max_steps), _dptr(out),
+                                   b(steps), b(res)), "btrt_solve_static")
+    return out, int(steps.value), float(res.value)
 
 
 def problem_from_workload(w, precision: int = F64, device: int = 0, check_interval: int = 1000) -> Problem:

@@ -18,7 +18,8 @@ SOURCES = [os.path.join(CSRC, f) for f in (
     "btrt_sweep_gen_f64.hip", "btrt_sweep_gen_f32.hip", "btrt_sweep_k0_f64.hip", "btrt_sweep_k0_f32.hip",
     "btrt_sweep_k0_f16dev.hip", "btrt_sweep_k0_bf16dev.hip",
     "btrt_batch_kernels.hip", "btrt_kernels.hip", "btrt3_kernels.hip",
-    "btrt_host.cpp", "btrt_group.cpp", "btrt_api.cpp", "btrt_batch.cpp", "btrt_server.cpp", "btrt3_api.cpp")]
+    "btrt_host.cpp", "btrt_group.cpp", "btrt_api.cpp", "btrt_batch.cpp", "btrt_server.cpp", "btrt3_api.cpp",
+    "btrt_static.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -35,25 +35,7 @@ using btrtk::LaunchCfg;
 
 // n steps as launches of the handle's shape; a count that is not a multiple of its steps per
 // launch ends with one shorter launch.
-int enqueue_steps(btrt* h, const LaunchCfg& want, int64_t n)
-{
-    if (n <= 0) return BTRT_OK;
-    if (n > h->inst.wall_limit - h->inst.step)
-        return fail(BTRT_E_INVAL, "%lld steps from step %lld go past the wall schedule (it ends at step %lld)",
-                    static_cast<long long>(n), static_cast<long long>(h->inst.step),
-                    static_cast<long long>(h->inst.wall_limit));
-    const LaunchCfg c = instance_resolve(h->inst, want);
-    for (int64_t i = 0; i < n;) {
-        LaunchCfg k = c;
-        k.steps = static_cast<int>(std::min<int64_t>(c.steps, n - i));
-        if (k.steps != 2) k.tile = 0;
-        if (k.steps == 1 && c.steps != 1) k.rows = k.group = 0;  // the one-step kernel's own tiles
-        int rc = instance_launch(h->inst, k, h->stream);
-        if (rc != BTRT_OK) return rc;
-        i += k.steps;
-    }
-    return BTRT_OK;
-}
+int enqueue_steps(btrt* h, const LaunchCfg& want, int64_t n) { return instance_steps(h->inst, want, n, h->stream); }
 
 int enqueue_steps(btrt* h, int64_t n) { return enqueue_steps(h, h->launch, n); }
 

@@ -6,8 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
-#include <string>
-#include <vector>
+#include <cstring>
 
 namespace btrth {
 
@@ -15,11 +14,12 @@ using namespace btrtk;
 
 
 namespace {
-thread_local std::string g_last_error;
+// The calling thread's last error message (a fixed buffer: reporting an error allocates nothing).
+thread_local char g_last_error[512];
 inline bool is_finite(double v) { return std::isfinite(v); }
 }  // namespace
 
-const char* last_error() { return g_last_error.c_str(); }
+const char* last_error() { return g_last_error; }
 
 int hip_fail(hipError_t e, const char* what)
 {
@@ -31,17 +31,36 @@ int fail(int code, const char* fmt, ...)
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);  // the arguments may point into g_last_error
     va_end(ap);
-    g_last_error = buf;
+    std::memcpy(g_last_error, buf, sizeof(buf));
     return code;
 }
 
 int ok()
 {
-    g_last_error.clear();
+    g_last_error[0] = '\0';
     return BTRT_OK;
 }
+
+namespace {
+// Copies count values value(0 .. count-1), converted to T, to device memory dst, staged through a
+// fixed buffer on the stack (no host allocation); synchronises s after each chunk.
+template <typename T, typename V>
+hipError_t upload_values(char* dst, size_t count, V value, hipStream_t s)
+{
+    constexpr size_t kChunk = 4096;
+    T buf[kChunk];
+    for (size_t at = 0; at < count; at += kChunk) {
+        const size_t m = std::min(kChunk, count - at);
+        for (size_t k = 0; k < m; ++k) buf[k] = static_cast<T>(value(at + k));
+        hipError_t e = hipMemcpyAsync(dst + at * sizeof(T), buf, m * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // buf is reused by the next chunk
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
 
 size_t pop_bytes(int precision)
 {
@@ -373,35 +392,28 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
         if (err != hipSuccess) return hip_fail(err, "hipStreamSynchronize");
     } else if (src_kind == BTRT_SRC_SIN) {
         const double pi = 3.14159265358979323846;
-        std::vector<double> sx(I.nx), sy(I.ny);
-        for (int i = 0; i < I.nx; ++i) sx[i] = std::sin(R->kx * pi * (i + 0.5) / I.nx);
-        for (int j = 0; j < I.ny; ++j) sy[j] = std::sin(R->ky * pi * (j + 0.5) / I.ny);
-        std::vector<float> fx, fy;
-        const void* px = sx.data();
-        const void* py = sy.data();
-        if (I.precision != BTRT_F64) {
-            fx.assign(sx.begin(), sx.end());
-            fy.assign(sy.begin(), sy.end());
-            px = fx.data();
-            py = fy.data();
+        auto sx = [&](size_t i) { return std::sin(R->kx * pi * (static_cast<double>(i) + 0.5) / I.nx); };
+        auto sy = [&](size_t j) { return std::sin(R->ky * pi * (static_cast<double>(j) + 0.5) / I.ny); };
+        if (I.precision == BTRT_F64) {
+            err = upload_values<double>(mem + I.L.src, static_cast<size_t>(I.nx), sx, s);
+            if (err == hipSuccess) err = upload_values<double>(mem + I.L.src_y, static_cast<size_t>(I.ny), sy, s);
+        } else {
+            err = upload_values<float>(mem + I.L.src, static_cast<size_t>(I.nx), sx, s);
+            if (err == hipSuccess) err = upload_values<float>(mem + I.L.src_y, static_cast<size_t>(I.ny), sy, s);
         }
-        err = hipMemcpyAsync(mem + I.L.src, px, I.nx * es, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess) err = hipMemcpyAsync(mem + I.L.src_y, py, I.ny * es, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) return hip_fail(err, "source table upload");
     }
     // Per-node A0(x): three planes (a11, a12, a22) in the phi type.
     if (I.afield) {
-        std::vector<double> comp(nn);
         for (int q = 0; q < 3 && err == hipSuccess; ++q) {
-            for (size_t k = 0; k < nn; ++k) comp[k] = K->field[3 * k + q];
             char* dst = mem + I.L.afield + q * static_cast<size_t>(I.plane) * es;
-            err = hipMemcpyAsync(tmp, comp.data(), nn * sizeof(double), hipMemcpyHostToDevice, s);
+            err = upload_values<double>(reinterpret_cast<char*>(tmp), nn, [&](size_t k) { return K->field[3 * k + q]; },
+                                        s);
             if (err == hipSuccess)
                 err = I.precision == BTRT_F64
                           ? launch_convert<double>(tmp, reinterpret_cast<double*>(dst), I.nx, I.ny, I.pitch, s)
                           : launch_convert<float>(tmp, reinterpret_cast<float*>(dst), I.nx, I.ny, I.pitch, s);
-            if (err == hipSuccess) err = hipStreamSynchronize(s);  // comp and tmp are reused
+            if (err == hipSuccess) err = hipStreamSynchronize(s);  // tmp is reused
         }
         if (err != hipSuccess) return hip_fail(err, "A0 field upload");
     }
@@ -467,61 +479,53 @@ SweepArgs<T> sweep_args(const Instance& I, int parity)
     return a;
 }
 
-std::vector<double> wall_entry_constants(const Instance& I)
+namespace {
+// Slot q of a wall-table entry built from the samples r of one step (wall_entry_values() of them):
+// the samples, then the corner means. Corner samples: x- and x+ at their first (y = 0) and last
+// (y = ny) sample, y- and y+ likewise at x = 0 and x = nx. A link through a corner takes the mean
+// of the two sides that meet there, computed in the storage type as the kernels compute it for
+// per-side constants.
+template <typename T, typename R>
+T wall_slot(const Instance& I, R r, size_t q)
 {
+    const size_t P = static_cast<size_t>(I.wall_entry_values());
+    if (q < P) return static_cast<T>(r(q));
     const size_t sx = 2 * static_cast<size_t>(I.ny) + 1, sy = 2 * static_cast<size_t>(I.nx) + 1;
-    std::vector<double> v(static_cast<size_t>(I.wall_entry_values()));
-    std::fill(v.begin(), v.begin() + sx, I.wall[0]);
-    std::fill(v.begin() + sx, v.begin() + 2 * sx, I.wall[1]);
-    std::fill(v.begin() + 2 * sx, v.begin() + 2 * sx + sy, I.wall[2]);
-    std::fill(v.begin() + 2 * sx + sy, v.end(), I.wall[3]);
-    return v;
+    const size_t xside[4] = {0, sx, 2 * sx - 1, sx - 1};                    // x- at y = 0, x+ at y = 0, x+ at ny, x- at ny
+    const size_t yside[4] = {2 * sx, 2 * sx + sy - 1, 2 * sx + 2 * sy - 1, 2 * sx + sy};  // y- at 0, y- at nx, y+ at nx, y+ at 0
+    const size_t c = q - P;
+    return T(0.5) * (static_cast<T>(r(xside[c])) + static_cast<T>(r(yside[c])));
 }
 
-namespace {
-template <typename T>
-std::vector<T> wall_entries(const Instance& I, const double* v, size_t rows)
+template <typename T, typename R>
+hipError_t upload_entries(const Instance& I, R r, size_t rows, char* dst, hipStream_t s)
 {
     const size_t P = static_cast<size_t>(I.wall_entry_values()), S = static_cast<size_t>(I.wall_entry_slots());
+    return upload_values<T>(dst, rows * S, [&](size_t k) {
+        const size_t row = k / S;
+        return wall_slot<T>(I, [&](size_t q) { return r(row * P + q); }, k - row * S);
+    }, s);
+}
+
+// Sample q of the per-side constants (the same value along each side).
+double constant_sample(const Instance& I, size_t q)
+{
     const size_t sx = 2 * static_cast<size_t>(I.ny) + 1, sy = 2 * static_cast<size_t>(I.nx) + 1;
-    std::vector<T> out(rows * S);
-    for (size_t k = 0; k < rows; ++k) {
-        const double* r = v + k * P;
-        T* o = out.data() + k * S;
-        for (size_t q = 0; q < P; ++q) o[q] = static_cast<T>(r[q]);
-        // Corner samples: x- and x+ at their first (y = 0) and last (y = ny) sample, y- and y+
-        // likewise at x = 0 and x = nx. A link through a corner takes the mean of the two sides
-        // that meet there, computed in the storage type as the kernels do for constant sides.
-        const T xm0 = o[0], xm1 = o[sx - 1], xp0 = o[sx], xp1 = o[2 * sx - 1];
-        const T ym0 = o[2 * sx], ym1 = o[2 * sx + sy - 1], yp0 = o[2 * sx + sy], yp1 = o[2 * sx + 2 * sy - 1];
-        o[P + 0] = T(0.5) * (xm0 + ym0);
-        o[P + 1] = T(0.5) * (xp0 + ym1);
-        o[P + 2] = T(0.5) * (xp1 + yp1);
-        o[P + 3] = T(0.5) * (xm1 + yp0);
-    }
-    return out;
+    return q < sx ? I.wall[0] : (q < 2 * sx ? I.wall[1] : (q < 2 * sx + sy ? I.wall[2] : I.wall[3]));
 }
 }  // namespace
 
 hipError_t upload_wall_values(const Instance& I, const double* v, size_t rows, char* dst, hipStream_t s)
 {
-    hipError_t e;
-    if (I.precision == BTRT_F64) {
-        const std::vector<double> d = wall_entries<double>(I, v, rows);
-        e = hipMemcpyAsync(dst, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host buffer is a local
-    } else {
-        const std::vector<float> f = wall_entries<float>(I, v, rows);
-        e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-    }
-    return e;
+    auto r = [v](size_t k) { return v[k]; };
+    return I.precision == BTRT_F64 ? upload_entries<double>(I, r, rows, dst, s) : upload_entries<float>(I, r, rows, dst, s);
 }
 
 hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s)
 {
-    const std::vector<double> v = wall_entry_constants(I);
-    return upload_wall_values(I, v.data(), 1, dst, s);
+    const size_t P = static_cast<size_t>(I.wall_entry_values());
+    auto r = [&I, P](size_t k) { return constant_sample(I, k % P); };
+    return I.precision == BTRT_F64 ? upload_entries<double>(I, r, 1, dst, s) : upload_entries<float>(I, r, 1, dst, s);
 }
 
 template <typename T>
@@ -576,6 +580,25 @@ int instance_launch(Instance& I, const LaunchCfg& cfg, hipStream_t s)
     if (e != hipSuccess) return hip_fail(e, "sweep launch");
     I.cur ^= 1;
     I.step += cfg.steps;
+    return BTRT_OK;
+}
+
+int instance_steps(Instance& I, const LaunchCfg& want, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return BTRT_OK;
+    if (n > I.wall_limit - I.step)
+        return fail(BTRT_E_INVAL, "%lld steps from step %lld go past the wall schedule (it ends at step %lld)",
+                    static_cast<long long>(n), static_cast<long long>(I.step), static_cast<long long>(I.wall_limit));
+    const LaunchCfg c = instance_resolve(I, want);
+    for (int64_t i = 0; i < n;) {
+        LaunchCfg k = c;
+        k.steps = static_cast<int>(std::min<int64_t>(c.steps, n - i));
+        if (k.steps != 2) k.tile = 0;
+        if (k.steps == 1 && c.steps != 1) k.rows = k.group = 0;  // the one-step kernel's own tiles
+        int rc = instance_launch(I, k, s);
+        if (rc != BTRT_OK) return rc;
+        i += k.steps;
+    }
     return BTRT_OK;
 }
 

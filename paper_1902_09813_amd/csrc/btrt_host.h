@@ -111,13 +111,13 @@ int instance_setup(Instance& I, const btrt_grid_t* grid, const btrt_flux_t* B, c
                    const btrt_source_t* R, const btrt_bc_t* bc, const Resolved& r, const double* phi0, char* mem,
                    hipStream_t s);
 
-// Wall samples of the per-side constants (one step of a schedule, wall_entry_values() values).
-std::vector<double> wall_entry_constants(const Instance& I);
 // Writes `rows` wall-table entries to device memory dst in I's phi type from rows of FP64
 // samples (wall_entry_values() each): the samples, then the mean of the two sides' samples at
 // each corner (x-y-, x+y-, x+y+, x-y+), rounded as the kernels round the mean of two per-side
-// constants. Synchronises s.
+// constants. Staged through a fixed host buffer (no allocation); synchronises s.
 hipError_t upload_wall_values(const Instance& I, const double* v, size_t rows, char* dst, hipStream_t s);
+// One wall-table entry of the per-side constants (the table of a general-model handle without a
+// schedule).
 hipError_t upload_wall_entry(const Instance& I, char* dst, hipStream_t s);
 
 // Sweep arguments with the buffer pointers for the given parity (0: f[0] -> f[1]).
@@ -129,6 +129,10 @@ GatherArgs<T> gather_args(const Instance& I);
 // One sweep launch of shape cfg (cfg.steps >= 1 time steps; automatic fields allowed); flips
 // the parity.
 int instance_launch(Instance& I, const btrtk::LaunchCfg& cfg, hipStream_t s);
+// n time steps as launches of shape `want` (automatic fields allowed); a count that is not a
+// multiple of its steps per launch ends with one shorter launch. Refuses steps past a wall
+// schedule's end (BTRT_E_INVAL, nothing enqueued).
+int instance_steps(Instance& I, const btrtk::LaunchCfg& want, int64_t n, hipStream_t s);
 // cfg with its automatic fields resolved for I's grid and format on the current device.
 btrtk::LaunchCfg instance_resolve(const Instance& I, const btrtk::LaunchCfg& cfg);
 // Enqueues the two-pass reduction (residual or error) into I's result slot (no sync).
