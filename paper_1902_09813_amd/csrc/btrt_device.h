@@ -476,10 +476,35 @@ struct WalkIn {
     int ok;              // bit 0: x-1 is a node, 1: x+1, 2: y-1, 3: y+1; bit 4: (x, r) is a node
 };
 
-template <typename F, bool WALLS, bool GEN>
-__device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int x, bool colok, int r, WalkIn<F>& in)
+// Rows of a periodic walk past its fill rows, as counters kept inside [0, ny): y[0] the row of
+// the next loads, y[l] the row level l updates. Every step moves each by one row, which needs a
+// compare and a select for any grid height, where wrapping a row number afresh needs a division.
+template <int K>
+struct WalkCursor {
+    int y[K + 1];
+};
+
+template <int K>
+__device__ __forceinline__ void cursor_start(WalkCursor<K>& c, int r, int ahead, int ny)
 {
-    const WalkRow w = walk_row(r, a.ny, WALLS ? a.pery : 1);
+    c.y[0] = wrap(r + ahead, ny);
+#pragma unroll
+    for (int l = 1; l <= K; ++l) c.y[l] = wrap(r - (l - 1), ny);
+}
+
+template <int K>
+__device__ __forceinline__ void cursor_next(WalkCursor<K>& c, int ny)
+{
+#pragma unroll
+    for (int l = 0; l <= K; ++l) c.y[l] = c.y[l] + 1 == ny ? 0 : c.y[l] + 1;
+}
+
+__device__ __forceinline__ WalkRow periodic_row(int y) { return WalkRow{y, true, true, true}; }
+
+template <typename F, bool WALLS, bool GEN>
+__device__ __forceinline__ void walk_load_row(const SweepArgs<typename F::T>& a, int x, bool colok, const WalkRow& w,
+                                              WalkIn<F>& in)
+{
     const int nx = a.nx, ny = a.ny, pitch = a.pitch, y = w.y;
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
     bool okxm = true, okxp = true, okym = true, okyp = true;
@@ -515,6 +540,12 @@ __device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int
         in.w[8] = (oxm || oyp) ? table_wall(a, x, y, 0, 8, oxm, oyp) : T(0);
     }
     in.ok = (okxm ? 1 : 0) | (okxp ? 2 : 0) | (okym ? 4 : 0) | (okyp ? 8 : 0) | ((colok && w.ok) ? 16 : 0);
+}
+
+template <typename F, bool WALLS, bool GEN>
+__device__ __forceinline__ void walk_load(const SweepArgs<typename F::T>& a, int x, bool colok, int r, WalkIn<F>& in)
+{
+    walk_load_row<F, WALLS, GEN>(a, x, colok, walk_row(r, a.ny, WALLS ? a.pery : 1), in);
 }
 
 // f(x, t) from the raw loads (bounce-back at Dirichlet walls, Eqs. (54)-(56)); zeros where the
@@ -577,20 +608,25 @@ constexpr int kAhead = sizeof(T) == 8 ? 1 : 2;
 
 // One row of the walk: level 1 on row r, levels 2..K on rows r-1 .. r-(K-1). PH picks which
 // of the two row buffers per level is current; the next call uses the other. `in` holds the
-// loads of row r and receives those of row r + kAhead.
-template <typename F, int SRC, int KM, int K, bool WALLS, int PH>
+// loads of row r and receives those of row r + kAhead. FULL: every level's row is valid and the
+// last level's row is an output row (the walk past its first 2 (K - 1) rows), so no row is
+// checked: the loop body has no branch per level.
+// With FULL on a grid periodic in both directions, rows come from the cursor `rows` (advanced
+// here) instead of being wrapped afresh.
+template <typename F, int SRC, int KM, int K, bool WALLS, int PH, bool FULL>
 __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, const WalkLane& L, int r, int r1,
-                                          WalkIn<F>& in, WalkState<typename F::T, K>& st)
+                                          WalkIn<F>& in, WalkState<typename F::T, K>& st, WalkCursor<K>& rows)
 {
     using T = typename F::T;
     constexpr bool GEN = (KM & kGen) != 0;
+    constexpr bool CURSOR = FULL && !WALLS;
     __builtin_amdgcn_s_barrier();
     Level<T> lev;
     walk_finish<F, WALLS, GEN>(a, in, lev.f, lev.phi);
 
     // Level 1: row r from global memory.
     {
-        const WalkRow w = walk_row(r, a.ny, a.pery);
+        const WalkRow w = CURSOR ? periodic_row(rows.y[1]) : walk_row(r, a.ny, a.pery);
         const int n = w.y * a.pitch + L.x;
         const T phi = collide<T, SRC, KM>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y, 0), n);
         F::settle(a, lev.f, phi);
@@ -604,7 +640,12 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
     // covers memory operations issued at least one row earlier.
     if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
     st.out_n = -1;
-    if (r + kAhead<T> < r1) walk_load<F, WALLS, GEN>(a, L.x, L.colok, r + kAhead<T>, in);
+    if (r + kAhead<T> < r1) {
+        if constexpr (CURSOR)
+            walk_load_row<F, WALLS, GEN>(a, L.x, L.colok, periodic_row(rows.y[0]), in);
+        else
+            walk_load<F, WALLS, GEN>(a, L.x, L.colok, r + kAhead<T>, in);
+    }
 
     // Levels 2..K: row r-(l-1) from the rows of level l-1. Level l is valid from row
     // ys-(K-l) on; the first rows of the walk (while the levels fill) are skipped, which leaves
@@ -612,11 +653,11 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
 #pragma unroll
     for (int l = 2; l <= K; ++l) {
         const int q = r - (l - 1);
-        const WalkRow w = walk_row(q, a.ny, a.pery);
+        const WalkRow w = CURSOR ? periodic_row(rows.y[l]) : walk_row(q, a.ny, a.pery);
         Level<T>& cur = st.mid[PH][l - 2];
         T g[9];
         T phi;
-        if (q >= L.ys - (K - l)) {
+        if (FULL || q >= L.ys - (K - l)) {
             phi = walk_collide<T, SRC, KM, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, l - 1, g);
         } else {
 #pragma unroll
@@ -632,13 +673,14 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
 #pragma unroll
             for (int i = 0; i < 9; ++i) lev.f[i] = g[i];
             lev.phi = phi;
-        } else if (L.store_col && q >= L.ys && q < L.ye) {
+        } else if (L.store_col && (FULL || (q >= L.ys && q < L.ye))) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) st.out.f[i] = g[i];
             st.out.phi = phi;
             st.out_n = w.y * a.pitch + L.x;
         }
     }
+    if constexpr (CURSOR) cursor_next(rows, a.ny);
 }
 
 // A workgroup of G = blockDim.x / 64 wavefronts (1 or kWalkGroup) holds G strips side by side
@@ -690,10 +732,23 @@ __device__ __forceinline__ void walk_strip(const SweepArgs<typename F::T>& a, in
     WalkIn<F> in[kAhead<T>];
     walk_load<F, WALLS, GEN>(a, L.x, L.colok, r0, in[0]);
     if (kAhead<T> == 2 && r0 + 1 < r1) walk_load<F, WALLS, GEN>(a, L.x, L.colok, r0 + 1, in[kAhead<T> - 1]);
-    for (int r = r0; r < r1; r += 2) {
-        walk_step<F, SRC, KM, K, WALLS, 0>(a, L, r, r1, in[0], st);
-        if (r + 1 < r1) walk_step<F, SRC, KM, K, WALLS, 1>(a, L, r + 1, r1, in[kAhead<T> - 1], st);
+    // The first 2 (K - 1) rows fill the levels: level l computes its first valid row at row
+    // r0 + 2 (l - 1) (its rows before that are not needed) and the last level stores from there on.
+    // That many rows (an even count, so the row buffers keep their parity) run with the checks;
+    // the rest of the walk has every level valid and stores every row.
+    const int fill = r0 + 2 * (K - 1) < r1 ? r0 + 2 * (K - 1) : r1;
+    WalkCursor<K> rows;
+    int r = r0;
+    for (; r < fill; r += 2) {
+        walk_step<F, SRC, KM, K, WALLS, 0, false>(a, L, r, r1, in[0], st, rows);
+        if (r + 1 < r1) walk_step<F, SRC, KM, K, WALLS, 1, false>(a, L, r + 1, r1, in[kAhead<T> - 1], st, rows);
     }
+    if constexpr (!WALLS) cursor_start(rows, r, kAhead<T>, ny);
+    for (; r + 1 < r1; r += 2) {
+        walk_step<F, SRC, KM, K, WALLS, 0, true>(a, L, r, r1, in[0], st, rows);
+        walk_step<F, SRC, KM, K, WALLS, 1, true>(a, L, r + 1, r1, in[kAhead<T> - 1], st, rows);
+    }
+    if (r < r1) walk_step<F, SRC, KM, K, WALLS, 0, true>(a, L, r, r1, in[0], st, rows);
     if (st.out_n >= 0) F::put(a, st.out_n, st.out.f, st.out.phi);
 }
 
