@@ -25,6 +25,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz.
+FP64_PEAK_TFLOPS = 78.6
+# FP64 lane-instruction issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (every FP64 VALU
+# instruction of a 64-wide wavefront occupies its SIMD for four cycles).
+FP64_ISSUE_PEAK_T = 39.3
+# One node update of the 4096^2 nonlinear workload (k0 = 1, K1 per node, Burgers flux, no source)
+# as the collision is written: FP64 flops (an FMA counts two) and FP64 VALU instructions.
+FLOPS_PER_UPDATE = 113
+FP64_INSTRUCTIONS_PER_UPDATE = 85
+BYTES_PER_UPDATE_F64 = 160  # 9 populations + phi read, the same written, per node update
 CHECK_INTERVAL = 1000
 METRIC = "MLUPS and % HBM roofline, batched/served vs plain; p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
@@ -205,7 +215,57 @@ def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=1200):
     return out
 
 
-def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 0, 0)):
+def precision_errors(w, steps):
+    """phi after ``steps`` steps from phi0 in every storage format (automatic launch shape) against
+    the FP64 field of the same run: normwise max, L2-relative and GRE (Eq. (63)) over the whole grid."""
+    from paper_1902_09813_amd import btrt
+
+    fields = {}
+    for name, prec in (("f64", btrt.F64), ("f32", btrt.F32), ("f16dev", btrt.F16DEV), ("bf16dev", btrt.BF16DEV)):
+        with btrt.Solver(btrt.problem_from_workload(w, precision=prec), w.phi0(), torch_memory=True) as s:
+            s.step(steps)
+            fields[name] = s.field()
+    ref = fields.pop("f64")
+    den_max, den_l2, den_l1 = np.max(np.abs(ref)), np.sqrt(np.sum(ref * ref)), np.sum(np.abs(ref))
+    out = {"steps": steps, "against": "FP64 field of the same run (held to the FP64 oracle at 1e-12 by the tests)"}
+    for name, phi in fields.items():
+        d = phi - ref
+        out[name] = {"max": float(np.max(np.abs(d)) / den_max), "l2": float(np.sqrt(np.sum(d * d)) / den_l2),
+                     "gre": float(np.sum(np.abs(d)) / den_l1)}
+    return out
+
+
+def _latency_stats(lat):
+    lat = np.sort(np.asarray(lat))
+    return round(float(np.percentile(lat, 50)), 3), round(float(np.percentile(lat, 99)), 3)
+
+
+def plain_requests(reqs):
+    """The same arrivals served one request at a time by plain single-handle solves (create, solve
+    to the same tolerance, read phi, destroy), in arrival order on one stream."""
+    import torch
+    from paper_1902_09813_amd import btrt
+
+    lat, updates = [], 0
+    start = time.perf_counter()
+    for t_arr, w, tol, ms in reqs:
+        now = time.perf_counter() - start
+        if now < t_arr:
+            time.sleep(t_arr - now)
+        p = btrt.problem_from_workload(w, precision=btrt.F32, check_interval=CHECK_INTERVAL)
+        with btrt.Solver(p, w.phi0()) as s:
+            steps, _ = s.solve(tol, ms)
+            s.field()
+        updates += w.nx * w.ny * steps
+        lat.append(time.perf_counter() - start - t_arr)
+    end = time.perf_counter() - start
+    torch.cuda.synchronize()
+    p50, p99 = _latency_stats(lat)
+    return {"p50_s": p50, "p99_s": p99, "aggregate_mlups": round(updates / end / 1e6, 1), "wall_s": round(end, 2)}
+
+
+def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 0, 0), min_requests=200,
+           plain=True):
     """Served solves: Poisson arrivals of FP32 requests (side 64..2048, residual <= 1e-8 or
     50000 steps) into the continuous-batching server. The arrival rate is 0.8 x the rate the
     server sustains on a backlog (calibration run). Time to solution is measured from each
@@ -229,7 +289,7 @@ def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 
                 srv.pump()
             sustain = calib_requests / (srv.clock() - t0)
         rate = 0.8 * sustain
-    n_req = max(4, int(rate * duration_s))
+    n_req = max(min_requests, int(rate * duration_s))
     reqs = W.c5(n_req, rate=rate, seed=seed)
     lat, done_ids = [], []
     with btrt.Server(**opts) as srv:
@@ -252,14 +312,14 @@ def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 
             info = srv.info(rid)
             lat.append(info["t_done"] - t_arr)
             steps.append(info["steps"])
-    lat = np.sort(np.array(lat))
-    return {
+    p50, p99 = _latency_stats(lat)
+    out = {
         "requests": n_req,
         "rate_per_s": round(rate, 3),
         "sustained_rate_per_s": round(sustain, 3) if sustain else None,
         "launch": list(launch),
-        "p50_s": round(float(np.percentile(lat, 50)), 3),
-        "p99_s": round(float(np.percentile(lat, 99)), 3),
+        "p50_s": p50,
+        "p99_s": p99,
         "mean_steps": round(float(np.mean(steps)), 1),
         "aggregate_mlups": round(st["node_updates"] / (end - start) / 1e6, 1),
         "wall_s": round(end - start, 2),
@@ -267,6 +327,12 @@ def served(duration_s=20.0, calib_requests=12, seed=5, rate=None, launch=(0, 0, 
         "failed": st["failed"],
         "memory_high_water_gb": round(st["memory_high_water"] / 1e9, 2),
     }
+    if plain:
+        print(f"[bench] served requests: the same {n_req} arrivals through plain per-request solves", file=sys.stderr,
+              flush=True)
+        out["plain_loop"] = plain_requests(reqs)
+        out["aggregate_speedup"] = round(out["aggregate_mlups"] / out["plain_loop"]["aggregate_mlups"], 2)
+    return out
 
 
 def _cpu_model():
@@ -280,32 +346,45 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(w, budget_s=12.0, budget_1thread_s=4.0):
-    """The FP64 oracle as it stands, on the host cores, for a bounded number of steps: all cores
-    (OpenMP over rows), then one thread."""
+def cpu_baseline(w3, w2, steps3=30, steps2=200, steps3_1=3, steps2_1=20, runs=3):
+    """The FP64 oracle as it stands, on the host cores: the median of ``runs`` timed runs of a
+    fixed number of steps, each from the same state after one untimed step, with every core
+    (OpenMP over rows) and with one thread, on the 4096^2 workload and on the 1024^2 one."""
     from oracle import oracle as O
     from tests._cases import oracle_problem, oracle_source
 
-    def timed(nthreads, budget):
+    def timed(w, nthreads, steps):
         o = O.Oracle(oracle_problem(w), w.phi0(), source=oracle_source(w), nthreads=nthreads)
-        t = time.perf_counter()
         o.step(1)
-        one = time.perf_counter() - t
-        n = max(1, min(200, int(budget / max(one, 1e-6))))
-        t = time.perf_counter()
-        o.step(n)
-        return n, time.perf_counter() - t
+        f0, p0 = o.f.copy(), o.phi_prev.copy()
+        times = []
+        for _ in range(runs):
+            o.f[...] = f0
+            o.phi_prev[...] = p0
+            t = time.perf_counter()
+            o.step(steps)
+            times.append(time.perf_counter() - t)
+        el = float(np.median(times))
+        return round(w.nx * w.ny * steps / el / 1e6, 3), el
 
-    n, el = timed(0, budget_s)
-    n1, el1 = timed(1, budget_1thread_s)
+    v3, el3 = timed(w3, 0, steps3)
+    v2, el2 = timed(w2, 0, steps2)
+    v3_1, el3_1 = timed(w3, 1, steps3_1)
+    v2_1, el2_1 = timed(w2, 1, steps2_1)
     return {
-        "value": round(w.nx * w.ny * n / el / 1e6, 3),
+        "value": v3,
         "unit": "MLUPS",
         "cores": O.threads(),
         "kind": "oracle",
-        "sample": f"{w.name}: {n} steps of the {w.nx}x{w.ny} grid after 1 warm-up step ({el:.1f} s)",
-        "value_1thread": round(w.nx * w.ny * n1 / el1 / 1e6, 3),
-        "sample_1thread": f"{n1} steps after 1 warm-up step, one thread ({el1:.1f} s)",
+        "sample": (f"{w3.name}: median of {runs} runs of {steps3} steps of the {w3.nx}x{w3.ny} grid after one "
+                   f"warm-up step ({el3:.2f} s each)"),
+        "value_1thread": v3_1,
+        "sample_1thread": f"median of {runs} runs of {steps3_1} steps, one thread ({el3_1:.2f} s each)",
+        "c2_value": v2,
+        "c2_sample": (f"{w2.name}: median of {runs} runs of {steps2} steps of the {w2.nx}x{w2.ny} grid ({el2:.2f} s "
+                      f"each)"),
+        "c2_value_1thread": v2_1,
+        "c2_sample_1thread": f"median of {runs} runs of {steps2_1} steps, one thread ({el2_1:.2f} s each)",
         "host_cpu": _cpu_model(),
     }
 
@@ -344,6 +423,49 @@ def valu_busy_for(precision_name, nodes, launch):
     return None if ent is None else ent.get("valu_busy")
 
 
+def roofline_of(r, precision_name):
+    """Roofline of the timed sweep kernel. One step per launch moves the whole state every step
+    and is bound by HBM: achieved = algorithmic bytes per launch / launch time against 8 TB/s. A
+    launch that fuses K steps reads and writes the state once for K node updates per node, so its
+    bytes per update fall by K and the FP64 arithmetic becomes the limit: achieved = FP64 flops of
+    the K updates / launch time against the FP64 vector peak (FP64 storage), with the HBM figures
+    beside it."""
+    k = r["launch"]["steps_per_launch"]
+    t = r["launch_ms_avg"] * 1e-3
+    nodes = r["nodes"]
+    bytes_per_launch = r["bytes_per_node_launch"] * nodes
+    hbm_launch = bytes_per_launch / t / 1e9
+    out = {
+        "kernel": "sweep_kernel" if k == 1 else ("sweep2_kernel" if r["launch"]["tile"] else "walk_kernel"),
+        "traffic": traffic_for(precision_name, nodes, r["launch"]),
+        "valu_busy": valu_busy_for(precision_name, nodes, r["launch"]),
+        "launch": r["launch"],
+        "launch_us_avg": round(t * 1e6, 2),
+        "hbm_per_launch": {"achieved": round(hbm_launch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(hbm_launch / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_per_launch},
+    }
+    if k == 1 or precision_name != "f64":
+        out.update({"bound": "hbm", "achieved": round(hbm_launch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_launch / HBM_PEAK_GBS, 4)})
+        return out
+    updates = nodes * k
+    tflops = FLOPS_PER_UPDATE * updates / t / 1e12
+    issue = FP64_INSTRUCTIONS_PER_UPDATE * updates / t / 1e12
+    out.update({
+        "bound": "alu",
+        "achieved": round(tflops, 2),
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+        "flops_per_update": FLOPS_PER_UPDATE,
+        "fp64_issue": {"instructions_per_update": FP64_INSTRUCTIONS_PER_UPDATE, "achieved": round(issue, 2),
+                       "peak": FP64_ISSUE_PEAK_T, "unit": "T lane-instructions/s",
+                       "frac": round(issue / FP64_ISSUE_PEAK_T, 4)},
+        "per_update_vs_one_step_hbm_roofline": round(BYTES_PER_UPDATE_F64 * updates / t / 1e9 / HBM_PEAK_GBS, 3),
+    })
+    return out
+
+
 def copy_probe(nbytes):
     """Device-to-device copy of a known size (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -369,7 +491,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and 1024^2 side measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the served measurement")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="arrival window of the served measurement (at least 200 requests arrive)")
+    ap.add_argument("--serve-requests", type=int, default=200, help="fewest requests of the served measurement")
+    ap.add_argument("--no-serve-plain", action="store_true",
+                    help="skip the plain per-request baseline of the served measurement")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--d3-launch", default="",
                     help="with --d3-only: fixed D3Q19 launch shape steps,z_chunk,tile (default: automatic)")
@@ -410,22 +536,7 @@ def main():
           flush=True)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     r = timed_run(w, prec, args.steps, args.warmup, args.fusion, launch)
-    bytes_per_launch = r["bytes_per_node_launch"] * r["nodes"]
-    achieved = bytes_per_launch / (r["launch_ms_avg"] * 1e-3) / 1e9
-    roofline = {
-        "bound": "hbm",
-        "kernel": ("sweep_kernel" if r["launch"]["steps_per_launch"] == 1 else
-                   "sweep2_kernel" if r["launch"]["tile"] else "walk_kernel"),
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(args.precision, r["nodes"], r["launch"]),
-        "valu_busy": valu_busy_for(args.precision, r["nodes"], r["launch"]),
-        "bytes_per_launch": bytes_per_launch,
-        "launch": r["launch"],
-        "launch_us_avg": round(r["launch_ms_avg"] * 1e3, 2),
-    }
+    roofline = roofline_of(r, args.precision)
     extra = {}
     if not args.no_extra:
         for name, other in precisions.items():
@@ -443,6 +554,9 @@ def main():
             extra[f"c3_{args.precision}_fusion{k}_mlups"] = round(rk["mlups"], 1)
             extra[f"c3_{args.precision}_fusion{k}_hbm_frac"] = round(
                 rk["bytes_per_node_launch"] * rk["nodes"] / (rk["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        print(f"[bench] side measurement: {w.name} reduced-precision errors after 5000 steps", file=sys.stderr,
+              flush=True)
+        extra["c3_precision_errors"] = precision_errors(w, 5000)
         w2 = W.c2()
         print(f"[bench] side measurement: {w2.name} f64", file=sys.stderr, flush=True)
         r3 = timed_run(w2, btrt.F64, 2000, 50, args.fusion)
@@ -457,11 +571,12 @@ def main():
         extra["batched_c4_f32"] = batched_vs_loop()
     if not args.no_serve:
         print("[bench] side measurement: served requests (continuous batching)", file=sys.stderr, flush=True)
-        extra["served_c5_f32"] = served(args.serve_seconds)
+        extra["served_c5_f32"] = served(args.serve_seconds, min_requests=args.serve_requests,
+                                        plain=not args.no_serve_plain)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, W.c2())
 
     line = {
         "metric": METRIC,

@@ -481,8 +481,9 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued);
 /* State of request id. Errors: BTRT_E_INVAL for an unknown or collected id. */
 int btrt_server_info(const btrt_server_t* s, int64_t id, btrt_request_info_t* info);
 
-/* phi of a DONE request into phi_out[nx*ny]; releases the request. Errors: BTRT_E_INVAL for an
- * unknown id or a request that is not DONE. */
+/* phi of a DONE request into phi_out[nx*ny]; releases the request. A FAILED request is released
+ * too and its error returned (BTRT_E_UNSTABLE, or the device error that ended it; phi_out is not
+ * written). Errors: BTRT_E_INVAL for an unknown id or a request still queued or running. */
 int btrt_server_result(btrt_server_t* s, int64_t id, double* phi_out);
 
 int btrt_server_stats(const btrt_server_t* s, btrt_server_stats_t* stats);

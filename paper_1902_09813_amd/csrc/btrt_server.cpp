@@ -305,6 +305,10 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued)
         int bad = 0;
         if (rc == BTRT_OK) rc = group_residuals(s->group, res.data(), &bad);
         if (rc == BTRT_OK) {
+            // Every member is either kept or retired (its arena block released) in this pass, and
+            // the kept list replaces the active one whatever happens: a retired request never
+            // stays in the group. A request whose result cannot be read back fails alone; the
+            // round reports the first such error after finishing the pass.
             std::vector<int64_t> keep;
             for (size_t k = 0; k < s->active.size(); ++k) {
                 Request& r = *s->req[s->active[k]];
@@ -315,14 +319,19 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued)
                     retire(s, r, BTRT_REQ_FAILED, BTRT_E_UNSTABLE);
                 } else if (res[k] <= r.tol || r.inst.step >= r.max_steps) {
                     r.result.resize(static_cast<size_t>(r.inst.nx) * r.inst.ny);
-                    rc = instance_gather(r.inst, -1, r.result.data(), s->stream);
-                    if (rc != BTRT_OK) break;
-                    retire(s, r, BTRT_REQ_DONE, BTRT_OK);
+                    const int grc = instance_gather(r.inst, -1, r.result.data(), s->stream);
+                    if (grc != BTRT_OK) {
+                        r.result.clear();
+                        retire(s, r, BTRT_REQ_FAILED, grc);
+                        if (rc == BTRT_OK) rc = grc;
+                    } else {
+                        retire(s, r, BTRT_REQ_DONE, BTRT_OK);
+                    }
                 } else {
                     keep.push_back(r.id);
                 }
             }
-            if (rc == BTRT_OK) s->active.swap(keep);
+            s->active.swap(keep);
         }
     }
     s->st.busy_seconds += s->now() - t_in;
@@ -346,6 +355,12 @@ int btrt_server_result(btrt_server_t* s, int64_t id, double* phi_out)
     auto it = s->req.find(id);
     if (it == s->req.end() || !phi_out) return fail(BTRT_E_INVAL, "unknown request %lld", static_cast<long long>(id));
     Request& r = *it->second;
+    if (r.info.status == BTRT_REQ_FAILED) {
+        // A failed request has no result; collecting it releases it and reports its error.
+        const int err = r.info.error != BTRT_OK ? r.info.error : BTRT_E_DEVICE;
+        s->req.erase(it);
+        return fail(err, "request %lld failed", static_cast<long long>(id));
+    }
     if (r.info.status != BTRT_REQ_DONE) return fail(BTRT_E_INVAL, "request %lld is not done", static_cast<long long>(id));
     std::copy(r.result.begin(), r.result.end(), phi_out);
     s->req.erase(it);

@@ -49,3 +49,26 @@ def test_traffic_record_lookup():
     assert bench.traffic_for("f64", nodes, dict(shape, strip_rows=8)) is None  # a shape not measured
     assert bench.traffic_key("f32", dict(steps_per_launch=4, strip_rows=32, strips_per_group=4, tile=0)) == \
         "f32_k4_r32_g4_t0"
+
+
+def _run(k, us, nodes=4096 * 4096, tile=0):
+    return {"launch": dict(steps_per_launch=k, strip_rows=64, strips_per_group=1, tile=tile), "launch_ms_avg": us * 1e-3,
+            "nodes": nodes, "bytes_per_node_launch": 160.0}
+
+
+def test_roofline_bound_follows_the_launch_shape():
+    # One step per launch: HBM-bound, algorithmic bytes per launch over 8 TB/s.
+    r1 = bench.roofline_of(_run(1, 495.0), "f64")
+    assert r1["bound"] == "hbm" and r1["unit"] == "GB/s"
+    assert r1["achieved"] == pytest.approx(160 * 4096 * 4096 / 495e-6 / 1e9, rel=1e-3)
+    assert r1["frac"] == pytest.approx(r1["achieved"] / 8000.0, rel=1e-3)
+    # Seven steps per launch: the FP64 arithmetic of 7 node updates per node bounds the launch;
+    # the per-launch HBM view stays beside it and every fraction is of a bound that holds.
+    r7 = bench.roofline_of(_run(7, 700.0), "f64")
+    assert r7["bound"] == "alu" and r7["unit"] == "TFLOP/s" and r7["peak"] == 78.6
+    flops = bench.FLOPS_PER_UPDATE * 7 * 4096 * 4096 / 700e-6 / 1e12
+    assert r7["achieved"] == pytest.approx(flops, rel=1e-3)
+    assert 0 < r7["frac"] < 1 and 0 < r7["fp64_issue"]["frac"] < 1 and 0 < r7["hbm_per_launch"]["frac"] < 1
+    assert r7["per_update_vs_one_step_hbm_roofline"] == pytest.approx(160 * 7 * 4096 * 4096 / 700e-6 / 8e12, rel=1e-3)
+    # Other storage formats report the per-launch HBM view.
+    assert bench.roofline_of(_run(7, 400.0), "f32")["bound"] == "hbm"

@@ -118,6 +118,15 @@ def test_unstable_request_fails_alone():
         assert srv.info(rb)["status"] == btrt.REQ_FAILED and srv.info(rb)["error"] == btrt.E_UNSTABLE
         for rid in ids:
             assert srv.info(rid)["status"] == btrt.REQ_DONE
+        # Collecting the failed request reports its error and releases it; nothing stays resident.
+        with pytest.raises(btrt.BtrtError) as e:
+            srv.result(rb)
+        assert e.value.code == btrt.E_UNSTABLE
+        with pytest.raises(btrt.BtrtError) as e:
+            srv.info(rb)
+        assert e.value.code == btrt.E_INVAL
+        st = srv.stats()
+        assert st["active"] == 0 and st["failed"] == 1
 
 
 def test_fp64_served_result_matches_oracle():

@@ -6,8 +6,9 @@ Dirichlet values that change along the walls and in time.
   wave speed carries (delta + 1)^2; the speed as printed leaves a residual.
 * Tables 4 and 5 (OB-TriRT row; dx = 1/40, c = 5, b = 0.05, delta = 1.5): the global relative
   errors (Eq. (63)) at t = 1 to the printed digits (2e-4 relative; the printed values carry five
-  significant digits), with the walls evaluated where each link meets them. a = 4 is not
-  reproduced (the run diverges) and is not tested.
+  significant digits), with the walls evaluated where each link meets them; the LBGK and RLBM rows
+  of both tables too. The OB-TriRT entry for a = 4 (2.2140e-3) is what the scheme gives with
+  k2 = 1 (the RLBM choice) to all printed digits; with the k2 of Eq. (62) that run diverges.
 * Walls that vary along a side: with Dirichlet values taken where each link meets the wall, a
   linear field is an exact steady state of the scheme (no convection, no source; any k0, K1, K2),
   to rounding; values taken level with the node instead (half a spacing off for diagonal links)
@@ -67,6 +68,34 @@ def test_tables_4_5(a, alpha, printed):
     assert w.nx == 120 and w.steps == 200
     g = O.gre(run_oracle(w).phi(), exact(w, w.steps))
     assert g == pytest.approx(printed, rel=2e-4), g
+
+
+def _bfe_gre(a, alpha, model="OB-TriRT"):
+    w = W.bfe(n=40, alpha=alpha, a=a, t_end=1.0)
+    if model == "LBGK":
+        w.k0 = w.k2 = O.k1_isotropic(w.A0[0])
+    elif model == "RLBM":
+        w.k0, w.k2 = 1.0, 1.0
+    phi = run_oracle(w).phi()
+    return O.gre(phi, exact(w, w.steps)) if np.all(np.isfinite(phi)) else float("nan")
+
+
+# LBGK: k0 = k1 = k2 = 1/tau (Table 1); RLBM: k0 = 1, k2 = 1 with k1 from Eq. (30).
+@pytest.mark.parametrize("model,a,alpha,printed", [
+    ("LBGK", 1.0, 0.05, 1.1958e-3), ("LBGK", 2.0, 0.05, 3.2058e-3), ("LBGK", 3.0, 0.05, 4.1915e-3),
+    ("RLBM", 1.0, 0.05, 5.2339e-4), ("RLBM", 2.0, 0.05, 9.9594e-4), ("RLBM", 3.0, 0.05, 1.1328e-3),
+    ("LBGK", 2.0, 0.1, 5.7829e-3), ("RLBM", 2.0, 0.005, 4.7209e-3), ("RLBM", 2.0, 0.1, 1.8174e-3),
+    ("RLBM", 2.0, 0.5, 1.7866e-3)])
+def test_tables_4_5_other_models(model, a, alpha, printed):
+    g = _bfe_gre(a, alpha, model)
+    assert g == pytest.approx(printed, rel=2e-4), g
+
+
+def test_table4_a4_entry_is_the_k2_one_scheme():
+    # The printed OB-TriRT entry at a = 4 is reproduced by k2 = 1 (Section 4.2.1's choice for
+    # anisotropic problems), not by the k2 of Eq. (62), with which the run diverges here.
+    assert _bfe_gre(4.0, 0.05, "RLBM") == pytest.approx(2.2140e-3, rel=2e-4)
+    assert np.isnan(_bfe_gre(4.0, 0.05))
 
 
 def test_second_order_in_space():
