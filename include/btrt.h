@@ -445,7 +445,10 @@ typedef struct {
     int32_t check_interval;     /* steps per round; the residual is checked after each round */
     btrt_batch_config_t launch; /* launch configuration of the batched sweeps; steps_per_launch
                                    0: chosen per round (two-step tiles below 2^21 resident nodes,
-                                   four-step walkers with 16-row strips from there on) */
+                                   four-step walkers with 16-row strips from there on), and a
+                                   request of 2^20 nodes or more, which fills the GPU alone, then
+                                   advances by launches of its own in the automatic single-grid
+                                   shape of btrt_step (the same bits) */
 } btrt_server_opts_t;
 
 typedef struct {

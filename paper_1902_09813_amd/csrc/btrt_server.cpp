@@ -100,6 +100,12 @@ struct Request {
 // Resident nodes from which an automatic launch configuration uses the strip walkers (measured
 // on gfx950 with the served workload: below it the rounds are latency-bound).
 constexpr int64_t kAutoWalkNodes = int64_t(1) << 21;
+// With the automatic launch configuration, a request of at least this many nodes fills the GPU by
+// itself: it advances by its own launches in the automatic single-grid shape (the seven-step
+// walker on large periodic grids) instead of sharing the batched launch of the smaller requests,
+// whose strips are shorter and whose launch shape suits small grids. Every shape gives the same
+// bits, so a result is the same either way.
+constexpr int64_t kSoloNodes = int64_t(1) << 20;
 
 struct btrt_server {
     int device = 0;
@@ -128,6 +134,31 @@ struct btrt_server {
 };
 
 namespace {
+
+bool solo(const btrt_server* s, const Instance& I)
+{
+    return s->auto_launch && static_cast<int64_t>(I.nx) * I.ny >= kSoloNodes;
+}
+
+// Eq. (64) residual of every active request into out (NaN for a non-finite phi): one reduction per
+// request, then one synchronisation.
+int residuals(btrt_server* s, double* out)
+{
+    double* h = s->group.h_res;  // pinned, max_active slots
+    for (size_t k = 0; k < s->active.size(); ++k) {
+        Instance& I = s->req[s->active[k]]->inst;
+        int rc = instance_reduce_async(I, btrtk::kResidual, s->stream);
+        if (rc == BTRT_OK) rc = instance_result_async(I, h + k * btrtk::kReducePartials, s->stream);
+        if (rc != BTRT_OK) return rc;
+    }
+    const hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (size_t k = 0; k < s->active.size(); ++k) {
+        const double* v = h + k * btrtk::kReducePartials;
+        out[k] = v[5] > 0 ? NAN : (v[1] > 0 ? v[0] / v[1] : (v[0] > 0 ? INFINITY : 0.0));
+    }
+    return BTRT_OK;
+}
 
 void release(btrt_server* s)
 {
@@ -287,7 +318,10 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued)
     int rc = admit(s);
     if (rc == BTRT_OK && s->dirty) {
         s->group.inst.clear();
-        for (int64_t id : s->active) s->group.inst.push_back(&s->req[id]->inst);
+        for (int64_t id : s->active) {
+            Instance& I = s->req[id]->inst;
+            if (!solo(s, I)) s->group.inst.push_back(&I);
+        }
         rc = group_upload(s->group);
         s->dirty = false;
     }
@@ -297,13 +331,16 @@ int btrt_server_pump(btrt_server_t* s, int32_t* active, int32_t* queued)
             // tiles finish them sooner; from kAutoWalkNodes on, four-step strip walkers (16-row
             // strips) move the state once per four steps. Every configuration gives the same bits.
             int64_t nodes = 0;
-            for (int64_t id : s->active) nodes += static_cast<int64_t>(s->req[id]->inst.nx) * s->req[id]->inst.ny;
+            for (const Instance* I : s->group.inst) nodes += static_cast<int64_t>(I->nx) * I->ny;
             s->group.cfg = nodes >= kAutoWalkNodes ? btrt_batch_config_t{4, 0, 0, 16} : btrt_batch_config_t{2, 0, 0, 0};
         }
         rc = group_enqueue(s->group, s->check_interval);
+        for (int64_t id : s->active) {
+            Instance& I = s->req[id]->inst;
+            if (rc == BTRT_OK && solo(s, I)) rc = instance_steps(I, btrtk::LaunchCfg{}, s->check_interval, s->stream);
+        }
         std::vector<double> res(s->active.size());
-        int bad = 0;
-        if (rc == BTRT_OK) rc = group_residuals(s->group, res.data(), &bad);
+        if (rc == BTRT_OK) rc = residuals(s, res.data());
         if (rc == BTRT_OK) {
             // Every member is either kept or retired (its arena block released) in this pass, and
             // the kept list replaces the active one whatever happens: a retired request never

@@ -169,3 +169,29 @@ def test_automatic_launch_switches_with_the_resident_work():
             with btrt.Solver(btrt.problem_from_workload(w, precision=btrt.F32, check_interval=200), w.phi0()) as s:
                 s.step(info["steps"])
                 assert np.array_equal(s.field(), srv.result(rid)), w.name
+
+
+@pytest.mark.parametrize("precision", [btrt.F32, btrt.F64], ids=["f32", "f64"])
+def test_large_requests_run_their_own_launches_with_the_same_bits(precision):
+    # Requests of 2^20 nodes and more advance by their own single-grid launches inside each round
+    # (automatic launch configuration); their results, and those of the small requests batched
+    # beside them, equal btrt_solve on single handles bit for bit, periodic and walled.
+    big = [W.c4(count=1, seed=41, side_range=(1024, 1024))[0], W.c4(count=1, seed=44, side_range=(1030, 1030))[0]]
+    small = [w for _, w, _, _ in W.c5(5, rate=1.0, seed=47, side_range=(40, 200))]
+    assert {w.bc_type[0] for w in big} == {btrt.PERIODIC, btrt.DIRICHLET}
+    work = [(w, 0.0 if i % 2 else 1e-7, 1600) for i, w in enumerate(big + small)]
+    say(f"[gpu] server with large requests {[w.nx for w in big]} and small ones {[w.nx for w in small]}")
+    with btrt.Server(precision=precision, check_interval=400, max_active=8, memory_bytes=8 << 30) as srv:
+        ids = []
+        for w, tol, ms in work:
+            ids.append(srv.submit(btrt.problem_from_workload(w, precision=precision, check_interval=400), w.phi0(),
+                                  tol, ms))
+            srv.pump()
+        drain(srv, ids)
+        for rid, (w, tol, ms) in zip(ids, work):
+            info = srv.info(rid)
+            got = srv.result(rid)
+            with btrt.Solver(btrt.problem_from_workload(w, precision=precision, check_interval=400), w.phi0()) as s:
+                steps, res = s.solve(tol, ms)
+                assert steps == info["steps"] and res == info["residual"], w.name
+                assert np.array_equal(s.field(), got), w.name
