@@ -554,6 +554,15 @@ def main():
             extra[f"c3_{args.precision}_fusion{k}_mlups"] = round(rk["mlups"], 1)
             extra[f"c3_{args.precision}_fusion{k}_hbm_frac"] = round(
                 rk["bytes_per_node_launch"] * rk["nodes"] / (rk["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        # One step per launch in the other plain format.
+        for name, other in (("f64", btrt.F64), ("f32", btrt.F32)):
+            if name == args.precision:
+                continue  # the fusion1 entry above
+            print(f"[bench] side measurement: {w.name} {name}, one step per launch", file=sys.stderr, flush=True)
+            rk = timed_run(w, other, min(args.steps, 1000), 20, 1)
+            extra[f"c3_{name}_fusion1_mlups"] = round(rk["mlups"], 1)
+            extra[f"c3_{name}_fusion1_hbm_frac"] = round(
+                rk["bytes_per_node_launch"] * rk["nodes"] / (rk["launch_ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         print(f"[bench] side measurement: {w.name} reduced-precision errors after 5000 steps", file=sys.stderr,
               flush=True)
         extra["c3_precision_errors"] = precision_errors(w, 5000)

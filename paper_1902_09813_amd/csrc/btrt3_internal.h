@@ -34,7 +34,7 @@ struct Sweep3 {
     T q2[6];            // K2 rates (k2_11, k2_12s, k2_13s, k2_22, k2_23s, k2_33), off-diagonals
                         // symmetrised (Eq. (100))
     int tiles_x, tiles_y;
-    int nts;            // 1: non-temporal stores
+    int nts;            // 1: the one-step kernel stores non-temporally (the launcher picks it)
     int zc;             // two-step kernel: output planes per workgroup
 };
 

@@ -74,10 +74,13 @@ __device__ __forceinline__ int xcd_tile()
     return k * q + (k < r ? k : r) + j;
 }
 
-template <typename T>
-__device__ __forceinline__ void store(T* p, T v, bool nontemporal)
+// NT: a non-temporal store, for the one-step kernel on boxes much larger than the caches. A
+// compile-time choice: with a run-time flag the compiler merges the two stores of the branch
+// into one and drops the hint. The two-step kernel stores normally.
+template <bool NT, typename T>
+__device__ __forceinline__ void store(T* p, T v)
 {
-    if (nontemporal)
+    if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
@@ -225,7 +228,7 @@ __device__ __forceinline__ bool node_of(const Sweep3<T>& a, int t, int& x, int& 
     return x < a.nx && y < a.ny;
 }
 
-template <typename T, bool SRC, bool KPHI>
+template <typename T, bool SRC, bool KPHI, bool NT>
 __global__ __launch_bounds__(kBlock) void sweep3_kernel(Sweep3<T> a)
 {
     int x, y, z;
@@ -236,8 +239,8 @@ __global__ __launch_bounds__(kBlock) void sweep3_kernel(Sweep3<T> a)
     const T s = SRC ? a.src[n] : T(0);
     const T phi = collide3<T, KPHI>(a, f, a.phi_prev[n], s);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) store(a.fout + i * a.plane + n, f[i], a.nts);
-    store(a.phi_out + n, phi, a.nts);
+    for (int i = 0; i < kQ; ++i) store<NT>(a.fout + i * a.plane + n, f[i]);
+    store<NT>(a.phi_out + n, phi);
 }
 
 // ---- two time steps per launch --------------------------------------------------------------
@@ -489,8 +492,8 @@ __global__ __launch_bounds__(TXH* TYH) void sweep3x2_kernel(Sweep3<T> a)
             const int n = pzz * a.slab + y * a.pitch + x;
             const T phi2 = collide3<T, KPHI>(a, g, prev_phi, SRC ? a.src[n] : T(0));
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) store(a.fout + i * a.plane + n, g[i], a.nts);
-            store(a.phi_out + n, phi2, a.nts);
+            for (int i = 0; i < kQ; ++i) store<false>(a.fout + i * a.plane + n, g[i]);
+            store<false>(a.phi_out + n, phi2);
         }
         __syncthreads();
         f5pp = keep[keep_pos(5)];
@@ -675,6 +678,23 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock
 
 }  // namespace
 
+template <typename T, bool NT>
+hipError_t launch3_one(const Sweep3<T>& a, bool src, bool k1_per_node, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (src) {
+        if (k1_per_node)
+            hipLaunchKernelGGL((sweep3_kernel<T, true, true, NT>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep3_kernel<T, true, false, NT>), grid, block, 0, s, a);
+    } else {
+        if (k1_per_node)
+            hipLaunchKernelGGL((sweep3_kernel<T, false, true, NT>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep3_kernel<T, false, false, NT>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch3_sweep(const Sweep3<T>& in, bool src, bool k1_per_node, hipStream_t s)
 {
@@ -684,18 +704,8 @@ hipError_t launch3_sweep(const Sweep3<T>& in, bool src, bool k1_per_node, hipStr
     const int64_t tiles = static_cast<int64_t>(a.tiles_x) * a.tiles_y * a.nz;
     if (tiles > INT32_MAX) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>(tiles)), block(kBlock);
-    if (src) {
-        if (k1_per_node)
-            hipLaunchKernelGGL((sweep3_kernel<T, true, true>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((sweep3_kernel<T, true, false>), grid, block, 0, s, a);
-    } else {
-        if (k1_per_node)
-            hipLaunchKernelGGL((sweep3_kernel<T, false, true>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((sweep3_kernel<T, false, false>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
+    return a.nts ? launch3_one<T, true>(a, src, k1_per_node, grid, block, s)
+                 : launch3_one<T, false>(a, src, k1_per_node, grid, block, s);
 }
 
 int64_t sweep2_workgroups(int nx, int ny, int nz, int tile, int zc)

@@ -7,7 +7,7 @@ namespace btrtk {
 
 template <typename T, int K0>
 hipError_t launch_batch_sweep_k0(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
-                                 int flip, int steps, int grid, int rows, hipStream_t s)
+                                 int flip, int steps, int grid, int rows, bool nts, hipStream_t s)
 {
     if (batch_walks(steps)) {
         // Several resident strips per CU: a persistent grid of `grid` blocks covers the list.
@@ -24,22 +24,28 @@ hipError_t launch_batch_sweep_k0(const BatchEntry<T>* ent, const int* begin, con
         return hipGetLastError();
     }
     const unsigned g = static_cast<unsigned>(grid > 0 ? std::min(grid, total_tiles) : total_tiles);
-    if (steps == 2)
-        hipLaunchKernelGGL((batch2_kernel<T, K0>), dim3(g), dim3(kBlock2), 0, s, ent, begin, par, ninst, total_tiles,
-                           flip);
+    if (steps == 2 && nts)
+        hipLaunchKernelGGL((batch2_kernel<T, K0, true>), dim3(g), dim3(kBlock2), 0, s, ent, begin, par, ninst,
+                           total_tiles, flip);
+    else if (steps == 2)
+        hipLaunchKernelGGL((batch2_kernel<T, K0, false>), dim3(g), dim3(kBlock2), 0, s, ent, begin, par, ninst,
+                           total_tiles, flip);
+    else if (nts)
+        hipLaunchKernelGGL((batch1_kernel<T, K0, true>), dim3(g), dim3(kBlock), 0, s, ent, begin, par, ninst,
+                           total_tiles, flip);
     else
-        hipLaunchKernelGGL((batch1_kernel<T, K0>), dim3(g), dim3(kBlock), 0, s, ent, begin, par, ninst, total_tiles,
-                           flip);
+        hipLaunchKernelGGL((batch1_kernel<T, K0, false>), dim3(g), dim3(kBlock), 0, s, ent, begin, par, ninst,
+                           total_tiles, flip);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
-                              int flip, int steps, int grid, int rows, bool k0one, hipStream_t s)
+                              int flip, int steps, int grid, int rows, bool k0one, bool nts, hipStream_t s)
 {
     if (total_tiles <= 0 || ninst <= 0) return hipSuccess;
-    return k0one ? launch_batch_sweep_k0<T, kK0One>(ent, begin, par, ninst, total_tiles, flip, steps, grid, rows, s)
-                 : launch_batch_sweep_k0<T, 0>(ent, begin, par, ninst, total_tiles, flip, steps, grid, rows, s);
+    return k0one ? launch_batch_sweep_k0<T, kK0One>(ent, begin, par, ninst, total_tiles, flip, steps, grid, rows, nts, s)
+                 : launch_batch_sweep_k0<T, 0>(ent, begin, par, ninst, total_tiles, flip, steps, grid, rows, nts, s);
 }
 
 int batch_strip_columns(int steps)
@@ -54,8 +60,8 @@ int tile_rows(int steps, int precision_bytes)
 }
 
 template hipError_t launch_batch_sweep<double>(const BatchEntry<double>*, const int*, const int*, int, int, int, int,
-                                               int, int, bool, hipStream_t);
+                                               int, int, bool, bool, hipStream_t);
 template hipError_t launch_batch_sweep<float>(const BatchEntry<float>*, const int*, const int*, int, int, int, int,
-                                              int, int, bool, hipStream_t);
+                                              int, int, bool, bool, hipStream_t);
 
 }  // namespace btrtk

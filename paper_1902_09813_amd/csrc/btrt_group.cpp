@@ -43,9 +43,10 @@ hipError_t raw_launch(Group& g, int steps, int flip)
     if (g.precision == BTRT_F64)
         return btrtk::launch_batch_sweep<double>(static_cast<const BatchEntry<double>*>(g.d_ent), g.d_begin[steps],
                                                  g.d_par, n, g.total[steps], flip, steps, grid_blocks(g), rows, k0one,
-                                                 g.stream);
+                                                 g.nts, g.stream);
     return btrtk::launch_batch_sweep<float>(static_cast<const BatchEntry<float>*>(g.d_ent), g.d_begin[steps], g.d_par,
-                                            n, g.total[steps], flip, steps, grid_blocks(g), rows, k0one, g.stream);
+                                            n, g.total[steps], flip, steps, grid_blocks(g), rows, k0one, g.nts,
+                                            g.stream);
 }
 
 // Offsets of each member's units in the concatenated list for `steps` per launch: 64 x rows
@@ -199,6 +200,7 @@ int group_upload(Group& g)
     double state = 0;
     for (const Instance* I : g.inst) state += 2.0 * 10.0 * I->plane * (g.precision == BTRT_F64 ? 8 : 4);
     const bool nts = state > 256.0 * 1024 * 1024;  // the members' state exceeds the Infinity Cache
+    g.nts = nts;
     if (e == hipSuccess) {
         if (g.precision == BTRT_F64) {
             std::vector<BatchEntry<double>> ent;

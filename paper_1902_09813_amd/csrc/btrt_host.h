@@ -159,6 +159,8 @@ struct Group {
     int total[btrtk::kBatchMaxSteps + 1] = {};
     int walk_rows[btrtk::kBatchMaxSteps + 1] = {};  // strip height each walker table was built for (0: not built)
     int flip = 0;       // launches since group_upload, mod 2
+    bool nts = false;   // the members' state exceeds the Infinity Cache: non-temporal stores in the
+                        // one- and two-step batch kernels
     btrt_batch_config_t cfg{2, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;

@@ -66,7 +66,8 @@ struct SweepArgs {
     T dev_scale, dev_inv; // 16-bit deviation formats: h = q(dev_scale (f+ - f_eq)), f+ = f_eq + h dev_inv
     int tiles_x, tiles_y; // set by the launcher for the kernel it picks
     int rows;             // rows per strip of the strip walkers (set by the launcher)
-    int nts;              // 1: non-temporal stores (grids much larger than the caches)
+    int nts;              // 1: the one-step and two-step tile kernels store non-temporally (grids
+                          // much larger than the caches; the launcher picks the kernel by it)
 };
 
 // Storage formats of the post-collision populations (kernels' template selector).
@@ -139,7 +140,7 @@ constexpr bool batch_steps_ok(int steps) { return steps == 1 || steps == 2 || ba
 constexpr int kBatchMaxSteps = 7;
 template <typename T>
 hipError_t launch_batch_sweep(const BatchEntry<T>* ent, const int* begin, const int* par, int ninst, int total_tiles,
-                              int flip, int steps, int grid, int rows, bool k0one, hipStream_t s);
+                              int flip, int steps, int grid, int rows, bool k0one, bool nts, hipStream_t s);
 int batch_strip_columns(int steps);
 // Tile height of the kernel that fuses `steps` steps (tile width is 64).
 int tile_rows(int steps, int precision_bytes);

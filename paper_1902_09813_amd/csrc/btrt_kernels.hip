@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(SweepArgs<typename F::T> a
     T f[9];
     init_values(phi0, x, y, a.nx, a.ny, a.perx, a.pery, c.wall, c.ab, c.cq, c.dq,
                 [&](int i, double v) { f[i] = static_cast<T>(v); });
-    F::put(a, y * a.pitch + x, f, static_cast<T>(phi0[k]));
+    F::template put<false>(a, y * a.pitch + x, f, static_cast<T>(phi0[k]));
 }
 
 template <typename T>
