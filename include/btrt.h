@@ -225,7 +225,9 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps);
  *                     read and written once per k steps. Step counts that are not a multiple of
  *                     k end with one shorter launch.
  *   strip_rows        rows per strip of the walkers (0: automatic, 8 .. 32 by grid size, up to
- *                     64 from six steps per launch on);
+ *                     64 from six steps per launch on; FP64 walkers from six steps on, which
+ *                     hold one wavefront per SIMD, take the height that fits every strip in
+ *                     the resident slots at once when that is 64 rows or more);
  *                     with one step per launch, the tile height 1, 2, 4, 8 or 16 (0: 4)
  *   strips_per_group  1 or 4 strips per workgroup, walked side by side in lockstep (0: auto)
  *   tile              1 with steps_per_launch 2: the two-step LDS tile kernel instead of a
@@ -250,11 +252,14 @@ int btrt_get_launch(btrt_t* h, btrt_launch_t* cfg);
 int btrt_set_fusion(btrt_t* h, int32_t steps_per_launch);
 
 /* Times candidate launch shapes on the handle's own state and keeps the fastest (per step):
- * one step per launch (tiles of 4, 8, 16 rows), the LDS tile, and strip walkers over 2 .. 7 steps x 8, 16, 32, 64, 128 rows
- * x 1, 4 strips per group, each for one untimed and two timed launches, as far as max_steps
- * allows. The state advances by *steps_used steps (the same bits btrt_step would give);
- * the Eq. (64) snapshot is not touched. Synchronises. best (may be NULL) receives the shape
- * kept, resolved. */
+ * the automatic shape, one step per launch (tiles of 4, 8, 16 rows), the LDS tile, strip walkers
+ * over 2 .. 7 steps x 8, 16, 32, 64, 128 rows x 1, 4 strips per group, and the automatic strip
+ * rows of six and seven steps, each for one untimed and one timed launch after a few warm-up
+ * launches of the automatic shape (at most max_steps / 10 steps); then the four fastest and the
+ * automatic shape again, in turn, twice over, one untimed and two timed launches each (the first
+ * pass may run while the GPU clocks still rise); as far as max_steps allows. The state advances by *steps_used steps (the same
+ * bits btrt_step would give); the Eq. (64) snapshot is not touched. Synchronises. best (may be
+ * NULL) receives the shape kept, resolved. */
 int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_used);
 
 /* phi(t) = sum_i f_i(x, t) (Eq. (9)) into phi_out[nx*ny]. Synchronises. */

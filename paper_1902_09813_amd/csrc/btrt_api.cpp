@@ -438,53 +438,90 @@ int btrt_tune(btrt_t* h, int64_t max_steps, btrt_launch_t* best, int64_t* steps_
     if (max_steps < 0) return fail(BTRT_E_INVAL, "max_steps < 0");
     max_steps = std::min<int64_t>(max_steps, h->inst.wall_limit - h->inst.step);  // stay inside a wall schedule
     DeviceGuard g(h->device);
-    // Candidates: one step per launch, the two-step LDS tile, and strip walkers over steps per
-    // launch x strip rows x strips per group. Each runs one untimed launch and kReps timed ones.
-    std::vector<LaunchCfg> cand{{1, 4, 0, 0}, {1, 8, 0, 0}, {1, 16, 0, 0}, {2, 0, 0, 1}};
+    // Candidates: the automatic shape (first), one step per launch, the two-step LDS tile, the
+    // automatic strip rows of six and seven steps, and strip walkers over steps per launch x strip
+    // rows x strips per group.
+    const LaunchCfg automatic = instance_resolve(h->inst, LaunchCfg{});
+    std::vector<LaunchCfg> cand{automatic, {1, 4, 0, 0}, {1, 8, 0, 0}, {1, 16, 0, 0}, {2, 0, 0, 1}, {6, 0, 0, 0},
+                                {7, 0, 0, 0}};
     for (int k = 2; k <= btrtk::kMaxFuse; ++k)
         for (int rows : {8, 16, 32, 64, 128})
             for (int grp : {1, btrtk::kWalkGroup}) cand.push_back(LaunchCfg{k, rows, grp, 0});
-    constexpr int kReps = 2;
-    std::vector<hipEvent_t> ev;
-    std::vector<size_t> timed;
     int64_t used = 0;
-    int rc = BTRT_OK;
-    for (size_t c = 0; c < cand.size() && rc == BTRT_OK; ++c) {
-        const int64_t need = static_cast<int64_t>(1 + kReps) * cand[c].steps;
-        if (used + need > max_steps) continue;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-            if (e0) (void)hipEventDestroy(e0);
-            rc = fail(BTRT_E_DEVICE, "hipEventCreate failed");
-            break;
+    // Times `list` (indices into cand): each candidate runs one untimed launch and `reps` timed
+    // ones, as far as max_steps allows; adds each one's time per step to ms_per_step and counts
+    // its timings in n.
+    auto time_list = [&](const std::vector<size_t>& list, int reps, std::vector<double>& ms_per_step,
+                         std::vector<int>& n) -> int {
+        std::vector<hipEvent_t> ev;
+        std::vector<size_t> timed;
+        int rc = BTRT_OK;
+        for (size_t c : list) {
+            const int64_t need = static_cast<int64_t>(1 + reps) * cand[c].steps;
+            if (used + need > max_steps) continue;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                if (e0) (void)hipEventDestroy(e0);
+                rc = fail(BTRT_E_DEVICE, "hipEventCreate failed");
+                break;
+            }
+            ev.push_back(e0);
+            ev.push_back(e1);
+            rc = enqueue_steps(h, cand[c], cand[c].steps);
+            if (rc == BTRT_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
+            if (rc == BTRT_OK) rc = enqueue_steps(h, cand[c], static_cast<int64_t>(reps) * cand[c].steps);
+            if (rc == BTRT_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
+            used += need;
+            timed.push_back(c);
+            if (rc != BTRT_OK) break;
         }
-        ev.push_back(e0);
-        ev.push_back(e1);
-        rc = enqueue_steps(h, cand[c], cand[c].steps);
-        if (rc == BTRT_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
-        if (rc == BTRT_OK) rc = enqueue_steps(h, cand[c], static_cast<int64_t>(kReps) * cand[c].steps);
-        if (rc == BTRT_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(BTRT_E_DEVICE, "hipEventRecord");
-        used += need;
-        timed.push_back(c);
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (rc == BTRT_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+        for (size_t j = 0; j < timed.size() && rc == BTRT_OK; ++j) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]) != hipSuccess) {
+                rc = fail(BTRT_E_DEVICE, "hipEventElapsedTime failed");
+                break;
+            }
+            ms_per_step[timed[j]] += ms / (reps * cand[timed[j]].steps);
+            ++n[timed[j]];
+        }
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+        return rc;
+    };
+    // Pass 1: every candidate, one timed launch, after a few warm-up launches of the automatic
+    // shape. It may still run while the GPU clocks rise, which favours the candidates timed last,
+    // so pass 2 re-times the kFinal fastest and the automatic shape in turn, twice over, two timed
+    // launches each, and keeps the lowest mean.
+    constexpr int kFinal = 4;
+    const int64_t warm = std::min<int64_t>(max_steps / 10, 8LL * automatic.steps);
+    if (warm > 0) {
+        int rc0 = enqueue_steps(h, automatic, warm);
+        if (rc0 != BTRT_OK) return rc0;
+        used += warm;
     }
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (rc == BTRT_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
-    double best_ms = -1.0;
-    LaunchCfg pick = h->launch;
-    for (size_t j = 0; j < timed.size() && rc == BTRT_OK; ++j) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]) != hipSuccess) {
-            rc = fail(BTRT_E_DEVICE, "hipEventElapsedTime failed");
-            break;
-        }
-        const double per_step = ms / (kReps * cand[timed[j]].steps);
-        if (best_ms < 0 || per_step < best_ms) {
-            best_ms = per_step;
-            pick = cand[timed[j]];
-        }
-    }
-    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    std::vector<double> t1(cand.size(), 0.0), t2(cand.size(), 0.0);
+    std::vector<int> n1(cand.size(), 0), n2(cand.size(), 0);
+    std::vector<size_t> all(cand.size());
+    for (size_t c = 0; c < cand.size(); ++c) all[c] = c;
+    int rc = time_list(all, 1, t1, n1);
+    std::vector<size_t> ranked;
+    for (size_t c = 0; c < cand.size(); ++c)
+        if (n1[c] > 0) ranked.push_back(c);
+    std::sort(ranked.begin(), ranked.end(), [&](size_t x, size_t y) { return t1[x] < t1[y]; });
+    if (ranked.size() > static_cast<size_t>(kFinal)) ranked.resize(kFinal);
+    if (n1[0] > 0 && std::find(ranked.begin(), ranked.end(), size_t{0}) == ranked.end()) ranked.push_back(0);
+    for (int round = 0; round < 2 && rc == BTRT_OK; ++round) rc = time_list(ranked, 2, t2, n2);
     if (rc != BTRT_OK) return rc;
+    LaunchCfg pick = h->launch;
+    double best_ms = -1.0;
+    for (size_t c : ranked) {
+        const double ms = n2[c] > 0 ? t2[c] / n2[c] : t1[c];  // pass 1 only when the steps ran out
+        if (best_ms < 0 || ms < best_ms) {
+            best_ms = ms;
+            pick = cand[c];
+        }
+    }
     h->launch = pick;
     if (best) *best = to_public(instance_resolve(h->inst, pick));
     if (steps_used) *steps_used = used;

@@ -948,8 +948,14 @@ int walk_waves_per_cu()
 //    launch from 2^20 nodes up (the state no longer fits the caches and the strip walkers cut its
 //    traffic; walled FP64 walkers beyond four steps hold one wavefront per SIMD and lose: 4096^2
 //    91k at four steps against 73k at seven), one per launch below;
-//  - strip rows: the largest of 64 (from six steps on), 32, 16, 8 that still gives every
-//    resident wavefront slot about two strips (rows at least 8);
+//  - strip rows: walkers that hold one wavefront per SIMD (FP64 from six steps on) take the
+//    height that fits all strips in the resident slots at once, when that is 64 rows or more:
+//    one round of long strips, so the 2(K - 1) fill rows of each strip are a small part of it
+//    and no second round starts on a partly idle chip (4096^2 FP64, K = 7: 342-row strips, 948
+//    strips for 1024 slots, 174k MLUPS against 163k with 64-row strips; K = 6: 316 rows, 159k
+//    against 147k); FP32 walkers (two wavefronts per SIMD) ran slower that way (4096^2, K = 7:
+//    164 rows 282k, 64 rows 285k). Otherwise the largest of 64 (from six steps on), 32, 16, 8
+//    that still gives every resident wavefront slot about two strips (rows at least 8);
 //  - strips per group: from six steps on 1 (one wavefront per SIMD); else kWalkGroup with 32-row
 //    strips (large grids), else 1.
 constexpr int kAutoDeep = 7;
@@ -960,6 +966,14 @@ void walk_shape(const SweepArgs<typename F::T>& a, LaunchCfg& cfg)
 {
     constexpr int W = Walk<K>::W;
     const int64_t strips_x = (a.nx + W - 1) / W;
+    if (cfg.rows <= 0 && K >= 6 && walk_waves_per_cu<F, SRC, KP, K>() <= 4) {
+        const int64_t slots = static_cast<int64_t>(device_cus()) * walk_waves_per_cu<F, SRC, KP, K>();
+        const int64_t per_column = slots / strips_x;
+        if (per_column >= 1) {
+            const int64_t rows = (a.ny + per_column - 1) / per_column;
+            if (rows >= 64) cfg.rows = static_cast<int>(rows);
+        }
+    }
     if (cfg.rows <= 0) {
         const int64_t want = 2LL * device_cus() * walk_waves_per_cu<F, SRC, KP, K>();
         cfg.rows = 8;

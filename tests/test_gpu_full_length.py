@@ -1,6 +1,7 @@
 """Full-length parity at the benchmark sizes against stored oracle results, in the automatic launch
-shape and in the shape the benchmark's tuner settles on (seven steps per launch with 64-row strips
-for the 4096^2 workload, the two-step LDS tile for the 1024^2 one; every shape gives the same bits,
+shape (for the 4096^2 workload seven steps per launch with strips tall enough for one round over
+the resident wavefront slots, the shape the benchmark's tuner settles on) and in a second one
+(64-row strips; the two-step LDS tile for the 1024^2 workload; every shape gives the same bits,
 tested at small sizes); and the error of every reduced-precision storage format at the same sizes.
 
 The oracle's full runs (1024 x 1024 for 20000 steps, 4096 x 4096 for 5000 steps) take minutes to an
