@@ -35,10 +35,11 @@ def test_traffic_record_lookup():
     nodes = 4096 * 4096
     if rec["kernel_sha256_16"] != bench.kernel_hash():
         # Counters taken on other kernel sources: the benchmark must report no traffic.
-        assert bench.traffic_for("f64", nodes, dict(steps_per_launch=7, strip_rows=64, strips_per_group=1,
+        assert bench.traffic_for("f64", nodes, dict(steps_per_launch=7, strip_rows=342, strips_per_group=1,
                                                     tile=0)) is None
         pytest.skip("the HBM counter record predates the current kernel sources")
-    shape = dict(steps_per_launch=7, strip_rows=64, strips_per_group=1, tile=0)
+    # The tuned shape of the FP64 workload: seven steps, strips tall enough for one round.
+    shape = dict(steps_per_launch=7, strip_rows=342, strips_per_group=1, tile=0)
     got = bench.traffic_for("f64", nodes, shape)
     alg = 160 * nodes
     assert got is not None and alg <= got <= 1.3 * alg
