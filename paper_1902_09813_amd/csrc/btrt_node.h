@@ -242,9 +242,13 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
         s = s + fmadd(T(1.5), R, -half * Rp);
     }
 
-    // K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)), per node when A depends on phi or on x
-    // (A = A0(x) (1 + beta phi^2), Eq. (73)).
-    T K11 = a.K11, K12 = a.K12, K22 = a.K22;
+    // Odd part: q = k0 j + dB - K1 h, h = j - B + dB/2, with K1 = (A / c_s^2 + I/2)^-1 (Eq. (30)).
+    // Per node when A depends on phi or on x (A = A0(x) (1 + beta phi^2), Eq. (73)): with
+    // M = 3 A + I/2, K1 h = adj(M) h / det M, the adjugate applied first and 1/det M taken into
+    // the last multiply-add (three multiplies fewer than forming K1).
+    const T k0 = K0ONE ? T(1) : a.k0;
+    const T hx = fmadd(half, dBx, jx - Bx), hy = fmadd(half, dBy, jy - By);
+    T qx, qy;
     if constexpr (K1M != kK1Const) {
         T a11 = a.a11, a12 = a.a12, a22 = a.a22;
         if constexpr (K1M == kK1Field) {
@@ -257,16 +261,14 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
         const T m12 = (T(3) * a12) * g;
         const T m22 = fmadd(T(3) * a22, g, half);
         const T rdet = recip(fmadd(m11, m22, -(m12 * m12)));
-        K11 = m22 * rdet;
-        K12 = -m12 * rdet;
-        K22 = m11 * rdet;
+        const T ux = fmadd(m22, hx, -(m12 * hy));
+        const T uy = fmadd(m11, hy, -(m12 * hx));
+        qx = fmadd(-rdet, ux, fmadd(k0, jx, dBx));
+        qy = fmadd(-rdet, uy, fmadd(k0, jy, dBy));
+    } else {
+        qx = fmadd(k0, jx, dBx) - fmadd(a.K11, hx, a.K12 * hy);
+        qy = fmadd(k0, jy, dBy) - fmadd(a.K12, hx, a.K22 * hy);
     }
-
-    // Odd part: q = k0 j + dB - K1 (j - B + dB/2).
-    const T k0 = K0ONE ? T(1) : a.k0;
-    const T hx = fmadd(half, dBx, jx - Bx), hy = fmadd(half, dBy, jy - By);
-    const T qx = fmadd(k0, jx, dBx) - fmadd(K11, hx, K12 * hy);
-    const T qy = fmadd(k0, jy, dBy) - fmadd(K12, hx, K22 * hy);
 
     // Even part: Q = (K2 - k0) o (P - d/3 I) with d = phi (D = phi I) or the general model's d.
     T d3 = third * phi;
