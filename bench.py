@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 78.6
-# FP64 lane-instruction issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (every FP64 VALU
-# instruction of a 64-wide wavefront occupies its SIMD for four cycles).
+# VALU lane-instruction issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (every FP64 VALU
+# instruction of a 64-wide wavefront occupies its SIMD for four cycles, and so does every FP32 or
+# 16-bit one that is not packed).
 FP64_ISSUE_PEAK_T = 39.3
 # One node update of the 4096^2 nonlinear workload (k0 = 1, K1 per node, Burgers flux, no source)
 # as the collision is written: FP64 flops (an FMA counts two) and FP64 VALU instructions.
@@ -423,13 +424,22 @@ def valu_busy_for(precision_name, nodes, launch):
     return None if ent is None else ent.get("valu_busy")
 
 
+def valu_lanes_for(precision_name, nodes, launch):
+    """VALU lane-instructions per node update (SQ_INSTS_VALU x 64 over the launch's updates), or
+    None if not measured for this shape and source."""
+    ent = counter_record(precision_name, nodes, launch)
+    return None if ent is None else ent.get("valu_lane_instructions_per_update")
+
+
 def roofline_of(r, precision_name):
     """Roofline of the timed sweep kernel. One step per launch moves the whole state every step
     and is bound by HBM: achieved = algorithmic bytes per launch / launch time against 8 TB/s. A
     launch that fuses K steps reads and writes the state once for K node updates per node, so its
-    bytes per update fall by K and the FP64 arithmetic becomes the limit: achieved = FP64 flops of
-    the K updates / launch time against the FP64 vector peak (FP64 storage), with the HBM figures
-    beside it."""
+    bytes per update fall by K and the arithmetic becomes the limit. FP64 storage: achieved = FP64
+    flops of the K updates / launch time against the FP64 vector peak. FP32 and 16-bit storage
+    (FP32 arithmetic, issued at the FP64 rate when not packed): achieved = the VALU lane-
+    instructions the counter record measured for the shape / launch time against the issue peak
+    (HBM as the bound when no record covers the shape). The HBM figures stand beside it."""
     k = r["launch"]["steps_per_launch"]
     t = r["launch_ms_avg"] * 1e-3
     nodes = r["nodes"]
@@ -444,11 +454,18 @@ def roofline_of(r, precision_name):
         "hbm_per_launch": {"achieved": round(hbm_launch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(hbm_launch / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_per_launch},
     }
+    updates = nodes * k
+    lanes = valu_lanes_for(precision_name, nodes, r["launch"]) if k > 1 and precision_name != "f64" else None
+    if lanes is not None:
+        issue = lanes * updates / t / 1e12
+        out.update({"bound": "alu", "achieved": round(issue, 2), "peak": FP64_ISSUE_PEAK_T,
+                    "unit": "T lane-instructions/s", "frac": round(issue / FP64_ISSUE_PEAK_T, 4),
+                    "valu_lane_instructions_per_update": lanes})
+        return out
     if k == 1 or precision_name != "f64":
         out.update({"bound": "hbm", "achieved": round(hbm_launch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_launch / HBM_PEAK_GBS, 4)})
         return out
-    updates = nodes * k
     tflops = FLOPS_PER_UPDATE * updates / t / 1e12
     issue = FP64_INSTRUCTIONS_PER_UPDATE * updates / t / 1e12
     out.update({

@@ -71,5 +71,16 @@ def test_roofline_bound_follows_the_launch_shape():
     assert r7["achieved"] == pytest.approx(flops, rel=1e-3)
     assert 0 < r7["frac"] < 1 and 0 < r7["fp64_issue"]["frac"] < 1 and 0 < r7["hbm_per_launch"]["frac"] < 1
     assert r7["per_update_vs_one_step_hbm_roofline"] == pytest.approx(160 * 7 * 4096 * 4096 / 700e-6 / 8e12, rel=1e-3)
-    # Other storage formats report the per-launch HBM view.
-    assert bench.roofline_of(_run(7, 400.0), "f32")["bound"] == "hbm"
+    # FP32 storage: the VALU issue of the lane-instructions the counter record counted for the
+    # shape when it covers it (the measured seven-step shape, on the current sources), else the
+    # per-launch HBM view.
+    r32 = bench.roofline_of(_run(7, 400.0), "f32")
+    lanes = bench.valu_lanes_for("f32", 4096 * 4096, r32["launch"])
+    if lanes is None:
+        assert r32["bound"] == "hbm"
+    else:
+        assert r32["bound"] == "alu" and r32["unit"] == "T lane-instructions/s" and r32["peak"] == 39.3
+        assert r32["achieved"] == pytest.approx(lanes * 7 * 4096 * 4096 / 400e-6 / 1e12, rel=1e-3)
+    unmeasured = _run(7, 400.0)
+    unmeasured["launch"]["strip_rows"] = 8
+    assert bench.roofline_of(unmeasured, "f32")["bound"] == "hbm"
