@@ -112,8 +112,9 @@ int btrt3_step(btrt3_t* h, int64_t n);
  *                     owns an xy tile of columns plus a one-column halo ring and walks z over a
  *                     chunk of planes: step 1 of each plane goes to LDS, step 2 of the plane below
  *                     is computed from it, so the state is read and written once per two steps.
- *   z_chunk           two-step launches: output planes per workgroup (0: automatic, about eight
- *                     workgroups per compute unit over the launch, at least 16 planes)
+ *   z_chunk           two-step launches: output planes per workgroup (0: automatic, the chunk of
+ *                     16 .. 64 planes that needs the fewest rounds of resident workgroups times
+ *                     planes walked, so the launch's last round is nearly full)
  *   tile              two-step launches, threads per workgroup (output columns): 1 = 64 x 8
  *                     (62 x 6), 2 = 32 x 16 (30 x 14), 3 = 32 x 8 (30 x 6), 4 = 16 x 16 (14 x 14);
  *                     0: automatic (1) */

@@ -62,6 +62,10 @@ template <typename T>
 hipError_t launch3_sweep2(const Sweep3<T>& a, bool src, bool k1_per_node, int tile, int zc, hipStream_t s);
 // Workgroups of a two-step launch for the grid (tile shape and z chunk as above).
 int64_t sweep2_workgroups(int nx, int ny, int nz, int tile, int zc);
+// Workgroups of the two-step kernel that one compute unit holds at once (its LDS and registers),
+// for the variant a launch with these arguments takes; 1 if the runtime cannot tell.
+template <typename T>
+int sweep2_blocks_per_cu(bool walls, bool src, bool k1_per_node, int tile);
 // f+(-1) and phi(-1) := phi0 (FP64 values converted to T) into a.fout / a.phi_out.
 template <typename T>
 hipError_t launch3_init(const Sweep3<T>& a, const double* phi0, hipStream_t s);

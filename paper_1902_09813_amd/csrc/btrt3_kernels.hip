@@ -717,6 +717,32 @@ int64_t sweep2_workgroups(int nx, int ny, int nz, int tile, int zc)
 }
 
 template <typename T, bool WALLS, int TXH, int TYH>
+int blocks_per_cu_shape(bool src, bool k1_per_node)
+{
+    using G = Tile3x2<TXH, TYH>;
+    int nb = 0;
+    hipError_t e;
+    if (src)
+        e = k1_per_node ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3x2_kernel<T, true, true, WALLS, TXH, TYH>, G::N, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3x2_kernel<T, true, false, WALLS, TXH, TYH>, G::N, 0);
+    else
+        e = k1_per_node ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3x2_kernel<T, false, true, WALLS, TXH, TYH>, G::N, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3x2_kernel<T, false, false, WALLS, TXH, TYH>, G::N, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <typename T>
+int sweep2_blocks_per_cu(bool walls, bool src, bool k1_per_node, int tile)
+{
+    switch (tile) {
+        case 2: return walls ? blocks_per_cu_shape<T, true, 32, 16>(src, k1_per_node) : blocks_per_cu_shape<T, false, 32, 16>(src, k1_per_node);
+        case 3: return walls ? blocks_per_cu_shape<T, true, 32, 8>(src, k1_per_node) : blocks_per_cu_shape<T, false, 32, 8>(src, k1_per_node);
+        case 4: return walls ? blocks_per_cu_shape<T, true, 16, 16>(src, k1_per_node) : blocks_per_cu_shape<T, false, 16, 16>(src, k1_per_node);
+        default: return walls ? blocks_per_cu_shape<T, true, 64, 8>(src, k1_per_node) : blocks_per_cu_shape<T, false, 64, 8>(src, k1_per_node);
+    }
+}
+
+template <typename T, bool WALLS, int TXH, int TYH>
 hipError_t launch3_sweep2_shape(Sweep3<T> a, bool src, bool k1_per_node, int zc, hipStream_t s)
 {
     using G = Tile3x2<TXH, TYH>;
@@ -809,6 +835,7 @@ hipError_t launch3_convert(const double* in, T* out, int nx, int ny, int nz, int
 #define BTRT3_INSTANTIATE(T)                                                                        \
     template hipError_t launch3_sweep<T>(const Sweep3<T>&, bool, bool, hipStream_t);                \
     template hipError_t launch3_sweep2<T>(const Sweep3<T>&, bool, bool, int, int, hipStream_t);     \
+    template int sweep2_blocks_per_cu<T>(bool, bool, bool, int);                                    \
     template hipError_t launch3_init<T>(const Sweep3<T>&, const double*, hipStream_t);              \
     template hipError_t launch3_gather<T>(const Gather3<T>&, hipStream_t);                          \
     template hipError_t launch3_reduce<T>(const Gather3<T>&, int, double*, hipStream_t);            \
