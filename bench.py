@@ -171,7 +171,7 @@ def timed_run3(w, precision, steps, warmup, launch=None):
             "hbm_frac": round(bw / HBM_PEAK_GBS, 4), "steps": steps}
 
 
-def batched_vs_loop(steps=2000, loop_steps=200, tune_steps=1200):
+def batched_vs_loop(steps=2600, loop_steps=200, tune_steps=1800):
     """The 256 uneven FP32 instances: one batched launch per fused step (tuned) against a loop
     of plain per-instance launches on one stream. Returns MLUPS of both."""
     import torch

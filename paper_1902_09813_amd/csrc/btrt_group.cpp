@@ -292,45 +292,78 @@ int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* 
     cand.push_back({4, 4, 16, 32});
     for (int gl : {0, 16}) cand.push_back({2, 0, gl, 0});
     cand.push_back({1, 0, 16, 0});
-    // Each candidate: k warm-up steps, then a timed run of a multiple of 16 k steps (one graph
-    // replay of 16 k-step launches); candidates whose replay does not fit the share of max_steps
-    // are skipped. Compared by time per step.
-    const int64_t share = max_steps / static_cast<int64_t>(cand.size());
+    // A few warm-up steps of the configuration in force, then pass 1: each candidate runs k untimed
+    // steps and one timed graph-replay's worth (16 launches of k steps), as far as three quarters
+    // of max_steps allow. Pass 1 may run while the GPU clocks still rise, which favours candidates
+    // timed late, so pass 2 re-times the kFinal fastest in turn, twice over, within the rest of
+    // max_steps, and the lowest mean time per step wins.
+    constexpr int kFinal = 3;
     const btrt_batch_config_t keep = g.cfg;
     int64_t used = 0;
-    double best_ms = INFINITY;
     btrt_batch_config_t best_cfg = keep;
     if (!g.inst.empty()) {
         hipEvent_t t0 = nullptr, t1 = nullptr;
-        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+            if (t0) (void)hipEventDestroy(t0);
             return fail(BTRT_E_DEVICE, "hipEventCreate");
+        }
         int rc = BTRT_OK;
-        for (const btrt_batch_config_t& c : cand) {
-            const int k = c.steps_per_launch;
-            const int64_t per = std::max<int64_t>(0, share - k) / (16 * k) * (16 * k);
-            if (per == 0) continue;
-            g.cfg = c;
-            rc = group_enqueue(g, k);
-            if (rc == BTRT_OK && c.graph_launches > 0) rc = build_graph(g);
-            if (rc != BTRT_OK) break;
+        std::vector<double> ms_sum(cand.size(), 0.0);
+        std::vector<int> n(cand.size(), 0);
+        // Times candidate c (k untimed steps, then 16 k timed) if it fits within `limit` steps.
+        auto time_one = [&](size_t c, int64_t limit) -> int {
+            const int k = cand[c].steps_per_launch;
+            const int64_t per = 16LL * k;
+            if (used + k + per > limit) return BTRT_OK;
+            g.cfg = cand[c];
+            int r = group_enqueue(g, k);
+            if (r == BTRT_OK && cand[c].graph_launches > 0) r = build_graph(g);
+            if (r != BTRT_OK) return r;
             (void)hipEventRecord(t0, g.stream);
-            rc = group_enqueue(g, per);
+            r = group_enqueue(g, per);
             (void)hipEventRecord(t1, g.stream);
             (void)hipEventSynchronize(t1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, t0, t1);
             used += k + per;
-            if (rc != BTRT_OK) break;
-            if (ms / per < best_ms) {
-                best_ms = ms / per;
-                best_cfg = c;
+            if (r == BTRT_OK) {
+                ms_sum[c] += ms / per;
+                ++n[c];
             }
+            return r;
+        };
+        const int64_t warm = std::min<int64_t>(max_steps / 10, 64) / keep.steps_per_launch * keep.steps_per_launch;
+        if (warm > 0) {
+            rc = group_enqueue(g, warm);
+            used += warm;
         }
+        for (size_t c = 0; c < cand.size() && rc == BTRT_OK; ++c) rc = time_one(c, max_steps * 3 / 4);
+        std::vector<size_t> ranked;
+        for (size_t c = 0; c < cand.size(); ++c)
+            if (n[c] > 0) ranked.push_back(c);
+        std::sort(ranked.begin(), ranked.end(), [&](size_t x, size_t y) { return ms_sum[x] < ms_sum[y]; });
+        if (ranked.size() > static_cast<size_t>(kFinal)) ranked.resize(kFinal);
+        std::vector<double> first(ms_sum);
+        std::vector<int> n1(n);
+        for (size_t c : ranked) {
+            ms_sum[c] = 0.0;
+            n[c] = 0;
+        }
+        for (int round = 0; round < 2 && rc == BTRT_OK; ++round)
+            for (size_t j = 0; j < ranked.size() && rc == BTRT_OK; ++j) rc = time_one(ranked[j], max_steps);
         (void)hipEventDestroy(t0);
         (void)hipEventDestroy(t1);
         if (rc != BTRT_OK) {
             g.cfg = keep;
             return rc;
+        }
+        double best_ms = INFINITY;
+        for (size_t c : ranked) {
+            const double ms = n[c] > 0 ? ms_sum[c] / n[c] : first[c] / n1[c];  // pass 1 only if the steps ran out
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_cfg = cand[c];
+            }
         }
     }
     g.cfg = best_cfg;
