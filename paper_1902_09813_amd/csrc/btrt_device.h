@@ -128,6 +128,13 @@ constexpr bool plain_format()
     return std::is_same<F, Plain<typename F::T>>::value;
 }
 
+// The collision's mode for storage format F: the kernel mode, plus kRcp1 for the 16-bit formats.
+template <typename F, int KM>
+constexpr int collide_mode()
+{
+    return plain_format<F>() ? KM : (KM | kRcp1);
+}
+
 // IEEE binary16, round to nearest even.
 struct F16Codec {
     __device__ __forceinline__ static unsigned short enc(float v) { return __builtin_bit_cast(unsigned short, static_cast<_Float16>(v)); }
@@ -219,7 +226,7 @@ __device__ __forceinline__ void tile1(const SweepArgs<typename F::T>& a, int tx,
     T f[9];
     F::template pull<(KM & kGen) != 0>(a, x, y, f);
     const int n = y * a.pitch + x;
-    const T phi = collide<T, SRC, KM>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y, 0), n);
+    const T phi = collide<T, SRC, collide_mode<F, KM>()>(a, f, a.phi_prev[n], source_at<T, SRC>(a, n, x, y, 0), n);
     F::template put<NT>(a, n, f, phi);
 }
 
@@ -298,7 +305,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         if (!live[j]) continue;
         const int s = static_cast<int>(threadIdx.x) + j * kBlock2;
         const int n = gys[j] * a.pitch + gxs[j];
-        const T phi = collide<T, SRC, KM>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j], 0), n);
+        const T phi = collide<T, SRC, collide_mode<F, KM>()>(a, f[j], pp[j], source_at<T, SRC>(a, n, gxs[j], gys[j], 0), n);
         F::settle(a, f[j], phi);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lf[i][s] = f[j][i];
@@ -335,7 +342,7 @@ __device__ __forceinline__ void tile2(const SweepArgs<typename F::T>& a, int tx,
         g[7] = (okxp && okyp) ? lf[7][l + EX + 1] : bounce(lf[5][l], tw5, wv(7, !okxp, !okyp));
         g[8] = (okxm && okyp) ? lf[8][l + EX - 1] : bounce(lf[6][l], tw5, wv(8, !okxm, !okyp));
         const int n = gy * a.pitch + gx;
-        const T phi = collide<T, SRC, KM>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy, 1), n);
+        const T phi = collide<T, SRC, collide_mode<F, KM>()>(a, g, lphi[l], source_at<T, SRC>(a, n, gx, gy, 1), n);
         F::template put<NT>(a, n, g, phi);
     }
 }
@@ -642,7 +649,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
     {
         const WalkRow w = CURSOR ? periodic_row(rows.y[1]) : walk_row(r, a.ny, a.pery);
         const int n = w.y * a.pitch + L.x;
-        const T phi = collide<T, SRC, KM>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y, 0), n);
+        const T phi = collide<T, SRC, collide_mode<F, KM>()>(a, lev.f, lev.phi, source_at<T, SRC>(a, n, L.x, w.y, 0), n);
         F::settle(a, lev.f, phi);
         lev.phi = phi;
         // Keep level 1 (and so the wait for its loads) ahead of the stores below.
@@ -672,7 +679,7 @@ __device__ __forceinline__ void walk_step(const SweepArgs<typename F::T>& a, con
         T g[9];
         T phi;
         if (FULL || q >= L.ys - (K - l)) {
-            phi = walk_collide<T, SRC, KM, WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, l - 1, g);
+            phi = walk_collide<T, SRC, collide_mode<F, KM>(), WALLS>(a, st.up[l - 2], cur, lev, L.x, L.okxm, L.okxp, w, l - 1, g);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = lev.f[i];

@@ -28,6 +28,9 @@ enum K1Mode : int { kK1Const = 0, kK1Phi = 1, kK1Field = 2 };
 constexpr int kK1Mask = 3;
 constexpr int kGen = 4;
 constexpr int kK0One = 8;
+// kRcp1 (set by the 16-bit deviation formats' call sites, not a kernel variant): the FP32 1/det M
+// of the per-node K1 from the hardware reciprocal and one Newton step instead of a division.
+constexpr int kRcp1 = 16;
 
 constexpr int kMaxFuse = 7;   // most time steps one sweep launch can fuse
 constexpr int kAutoFuse = 4;  // steps per launch of the automatic shape on large grids

@@ -28,14 +28,26 @@ __host__ __device__ inline T abspow(T x, T y)
         return pow(fabs(x), y);
 }
 
-// 1/d for the per-node K1. FP64: the hardware reciprocal refined by two Newton steps (within an
-// ulp of the quotient, and about half the instructions of an IEEE division, which matters in the
-// fused walkers where every level repeats it); FP32: a division.
-template <typename T>
+// 1/d for the per-node K1 (d = det M >= 1/4). FP64: the hardware reciprocal refined by two
+// Newton steps (within an ulp of the quotient, and about half the instructions of an IEEE
+// division, which matters in the fused walkers where every level repeats it). FP32: a division,
+// or with ONE_NEWTON the hardware reciprocal and one Newton step (within an ulp, a third of the
+// instructions; the 16-bit deviation formats, whose walkers keep the VALU busy every cycle, run
+// 5-6.5 % faster with it, while the FP32 seven-step walker's schedule ran 2 % slower).
+template <typename T, bool ONE_NEWTON = false>
 __host__ __device__ inline T recip(T d)
 {
     if constexpr (sizeof(T) == 4) {
-        return T(1) / d;
+        if constexpr (ONE_NEWTON) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            const T r = __builtin_amdgcn_rcpf(d);
+#else
+            const T r = T(1) / d;
+#endif
+            return fmadd(r, fmadd(-d, r, T(1)), r);
+        } else {
+            return T(1) / d;
+        }
     } else {
 #if defined(__HIP_DEVICE_COMPILE__)
         T r = __builtin_amdgcn_rcp(d);
@@ -260,7 +272,7 @@ __host__ __device__ inline T collide(const SweepArgs<T>& a, T f[9], T phi_prev, 
         const T m11 = fmadd(T(3) * a11, g, half);
         const T m12 = (T(3) * a12) * g;
         const T m22 = fmadd(T(3) * a22, g, half);
-        const T rdet = recip(fmadd(m11, m22, -(m12 * m12)));
+        const T rdet = recip<T, (KM & kRcp1) != 0>(fmadd(m11, m22, -(m12 * m12)));
         const T ux = fmadd(m22, hx, -(m12 * hy));
         const T uy = fmadd(m11, hy, -(m12 * hx));
         qx = fmadd(-rdet, ux, fmadd(k0, jx, dBx));
