@@ -111,3 +111,27 @@ def test_invalid_launch_shapes_are_rejected():
             with pytest.raises(btrt.BtrtError) as e:
                 s.set_launch(*bad)
             assert e.value.code == btrt.E_INVAL, bad
+
+
+@pytest.mark.parametrize("walls", [False, True], ids=["periodic", "walled"])
+def test_single_round_strips_are_bitwise_identical(walls):
+    # FP64 walkers from six steps per launch hold one wavefront per SIMD; their automatic strips
+    # are tall enough for one round over the resident slots only on large grids (2048^2: 40 strips
+    # across, 82 rows at K = 7), so the small grids above never take them. 15 steps: two 7-step
+    # launches and a 1-step one, or two 6-step launches and a 3-step one.
+    w = W.c3().scaled(2048, 2048, 0)
+    if walls:
+        w = W.Workload("walled_2048", 2048, 2048, 0, flux_b=w.flux_b, A0=w.A0, beta=w.beta, bc_type=(1, 1, 1, 1),
+                       bc_value=(0.2, -0.1, 0.5, 0.3), seed=11, phi0_kind="uniform")
+    steps = 15
+    say(f"[gpu] single-round strips {w.name} {w.nx}x{w.ny}, {steps} steps")
+    with btrt.Solver(btrt.problem_from_workload(w), w.phi0(), torch_memory=True) as ref:
+        ref.set_launch(1, 4, 1, 0).step(steps)
+        want = ref.populations()
+    for k in (6, 7):
+        with btrt.Solver(btrt.problem_from_workload(w), w.phi0(), torch_memory=True) as s:
+            s.set_launch(k, 0, 0, 0)
+            _, rows, group, _ = s.launch()
+            assert rows >= 64 and group == 1, s.launch()
+            s.step(steps)
+            assert np.array_equal(s.populations(), want), (k, rows)
