@@ -217,9 +217,10 @@ int btrt_set_walls(btrt_t* h, const double* values, int64_t steps);
 
 /* Shape of the sweep launches btrt_step makes. Every shape gives bitwise identical results;
  * only the speed differs. Zero fields are chosen by the library for the grid.
- *   steps_per_launch  1 .. 7 time steps per launch (0: 7 on grids periodic in x and y with
- *                     FP64/FP32 storage and the standard node model from 2^22 nodes up, else 4
- *                     from 2^20 nodes up, else 1). With
+ *   steps_per_launch  1 .. 7 time steps per launch (0: with FP64/FP32 storage and the standard
+ *                     node model from 2^22 nodes up 7, or 6 for FP64 with a Dirichlet wall,
+ *                     and for FP32 with a wall 7 from 2^24 nodes up; else 4 from 2^20 nodes
+ *                     up, else 1). With
  *                     k >= 2 each wavefront walks a strip of 66 - 2k columns down the grid and
  *                     keeps the k - 1 intermediate time levels in registers, so the state is
  *                     read and written once per k steps. Step counts that are not a multiple of

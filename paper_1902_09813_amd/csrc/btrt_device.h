@@ -948,13 +948,16 @@ int walk_waves_per_cu()
 }
 
 // Automatic launch shape (measured on gfx950 over 256^2 .. 4096^2 grids):
-//  - steps: kAutoDeep (7) per launch on grids periodic in x and y with plain FP64/FP32 storage
-//    and the standard node model from 2^22 nodes up (there the walkers are issue-bound and every
-//    further level saves a pass over the state: 4096^2 FP64 155k against 110k MLUPS at four
-//    steps, FP32 287k against 203k; 2048^2 FP64 120k against 93k); else kAutoFuse (4) per
-//    launch from 2^20 nodes up (the state no longer fits the caches and the strip walkers cut its
-//    traffic; walled FP64 walkers beyond four steps hold one wavefront per SIMD and lose: 4096^2
-//    91k at four steps against 73k at seven), one per launch below;
+//  - steps: kAutoDeep (7) per launch with plain FP64/FP32 storage and the standard node model
+//    from 2^22 nodes up (there the walkers are issue-bound and every further level saves a pass
+//    over the state: 4096^2 FP64 155k against 110k MLUPS at four steps, FP32 287k against 203k;
+//    2048^2 FP64 120k against 93k), kAutoDeepWalls (6) for FP64 with a Dirichlet wall (its
+//    seven-step walker carries the bounce-back registers: with the single-round strips below,
+//    4096^2 walled 123k MLUPS at six steps, 113k at seven, 110k at four; 2048^2 107k at six,
+//    95k at four), and for FP32 with a wall from 2^24 nodes up (4096^2 239k at seven steps
+//    against 201k at four, but 2048^2 160k against 173k); else kAutoFuse (4) per launch from
+//    2^20 nodes up (the state no longer fits the caches and the strip walkers cut its traffic),
+//    one per launch below;
 //  - strip rows: walkers that hold one wavefront per SIMD (FP64 from six steps on) take the
 //    height that fits all strips in the resident slots at once, when that is 64 rows or more:
 //    one round of long strips, so the 2(K - 1) fill rows of each strip are a small part of it
@@ -966,6 +969,7 @@ int walk_waves_per_cu()
 //  - strips per group: from six steps on 1 (one wavefront per SIMD); else kWalkGroup with 32-row
 //    strips (large grids), else 1.
 constexpr int kAutoDeep = 7;
+constexpr int kAutoDeepWalls = 6;
 
 
 template <typename F, int SRC, int KP, int K>
@@ -1000,8 +1004,9 @@ LaunchCfg resolve_variant(const SweepArgs<typename F::T>& a, LaunchCfg cfg)
 {
     if (cfg.steps <= 0) {
         const int64_t nodes = static_cast<int64_t>(a.nx) * a.ny;
-        const bool deep = plain_format<F>() && (KP & kGen) == 0 && a.perx && a.pery && nodes >= (1LL << 22);
-        cfg.steps = deep ? kAutoDeep : (nodes >= (1LL << 20) ? kAutoFuse : 1);
+        const bool fp64 = sizeof(typename F::T) == 8, periodic = a.perx && a.pery;
+        const bool deep = plain_format<F>() && (KP & kGen) == 0 && nodes >= (periodic || fp64 ? (1LL << 22) : (1LL << 24));
+        cfg.steps = deep ? (fp64 && !periodic ? kAutoDeepWalls : kAutoDeep) : (nodes >= (1LL << 20) ? kAutoFuse : 1);
     }
     if (cfg.steps != 2) cfg.tile = 0;
     if (cfg.steps == 1) {  // rows: tile height of the one-step kernel

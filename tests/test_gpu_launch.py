@@ -82,7 +82,7 @@ def test_automatic_shape_by_grid_size():
         k, rows, group, tile = s.launch()
         assert k == 4 and rows in (8, 16, 32) and group in (1, 4) and tile == 0
     # From 2^22 nodes: seven steps per launch, one strip per group, on periodic grids with plain
-    # storage; four with Dirichlet walls or 16-bit storage. FP64 seven-step walkers (one wavefront
+    # storage; four with 16-bit storage. FP64 seven-step walkers (one wavefront
     # per SIMD) take strips tall enough for one round over the resident slots: at 2048^2, 40
     # strips across, 82 rows (1000 strips) with 1024 slots.
     big = W.c3().scaled(2048, 2048, 0)
@@ -98,8 +98,19 @@ def test_automatic_shape_by_grid_size():
                 assert rows in (16, 32, 64), s.launch()
     with btrt.Solver(btrt.problem_from_workload(big, precision=btrt.F16DEV), big.phi0()) as s:
         assert s.launch()[0] == 4
+    # With Dirichlet walls: six steps per launch in FP64 from 2^22 nodes (the seven-step walker
+    # carries the bounce-back registers), in FP32 four below 2^24 nodes and seven from there;
+    # below 2^22 nodes four.
     walled = W.c2().scaled(2048, 2048, 0)
     with btrt.Solver(btrt.problem_from_workload(walled), walled.phi0()) as s:
+        assert s.launch()[0] == 6
+    with btrt.Solver(btrt.problem_from_workload(walled, precision=btrt.F32), walled.phi0()) as s:
+        assert s.launch()[0] == 4
+    big_walled = W.c2().scaled(4096, 4096, 0)
+    with btrt.Solver(btrt.problem_from_workload(big_walled, precision=btrt.F32), big_walled.phi0()) as s:
+        assert s.launch()[0] == 7
+    small = W.c2()
+    with btrt.Solver(btrt.problem_from_workload(small), small.phi0()) as s:
         assert s.launch()[0] == 4
 
 
