@@ -412,8 +412,9 @@ int btrt_batch_get_config(const btrt_batch_t* b, btrt_batch_config_t* cfg);
  * (11): walkers of 4, 6 and 7 steps with 16- and 32-row strips and 16-launch graphs; 4-step
  * walkers with 32-row strips without graphs and with 4 blocks per CU; 2 steps with and without
  * graphs; 1 step with graphs. After a warm-up of the configuration in force (at most
- * max_steps / 10 steps), each candidate takes k untimed steps (k steps per launch) and 16 k
- * timed ones, as far as three quarters of max_steps allow; then the three fastest run again in
+ * max_steps / 10 steps), each candidate takes k or 2 k untimed steps (k steps per launch; the
+ * timed run starts at the launch parity a graph replay starts from) and 16 k timed ones, as far
+ * as three quarters of max_steps allow; then the three fastest run again in
  * turn, twice over, within the rest, and the lowest mean wins (the first pass may run while
  * the GPU clocks still rise). *steps_used = steps taken. Synchronises. */
 int btrt_batch_tune(btrt_batch_t* b, int64_t max_steps, btrt_batch_config_t* best, int64_t* steps_used);

@@ -310,13 +310,16 @@ int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* 
         int rc = BTRT_OK;
         std::vector<double> ms_sum(cand.size(), 0.0);
         std::vector<int> n(cand.size(), 0);
-        // Times candidate c (k untimed steps, then 16 k timed) if it fits within `limit` steps.
+        // Times candidate c (k untimed steps, or 2 k so that the timed run starts at launch
+        // parity 0 where a graph replay starts, then 16 k timed) if it fits within `limit` steps.
         auto time_one = [&](size_t c, int64_t limit) -> int {
             const int k = cand[c].steps_per_launch;
             const int64_t per = 16LL * k;
-            if (used + k + per > limit) return BTRT_OK;
+            const int64_t warm_k = g.flip ? k : 2LL * k;  // each launch flips the parity
+            if (used + warm_k + per > limit) return BTRT_OK;
             g.cfg = cand[c];
-            int r = group_enqueue(g, k);
+            int r = group_enqueue(g, warm_k);
+            used += warm_k;
             if (r == BTRT_OK && cand[c].graph_launches > 0) r = build_graph(g);
             if (r != BTRT_OK) return r;
             (void)hipEventRecord(t0, g.stream);
@@ -325,7 +328,7 @@ int group_tune(Group& g, int64_t max_steps, btrt_batch_config_t* best, int64_t* 
             (void)hipEventSynchronize(t1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, t0, t1);
-            used += k + per;
+            used += per;
             if (r == BTRT_OK) {
                 ms_sum[c] += ms / per;
                 ++n[c];
